@@ -1,0 +1,190 @@
+"""FP64 CPU oracle for PlenOctree rendering -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this package.  The product library never does, and this package imports
+nothing from it: both sides receive the same seeded inputs from the scene
+generators and nothing else.
+
+The arithmetic lives in ``oracle.c`` (plain C, double precision, optional
+OpenMP over rays).  This module only compiles it with gcc and marshals NumPy
+arrays through ctypes.  See ``oracle.c`` for the passages of the paper each
+function follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_SO = os.environ.get("PO_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def build(force: bool = True) -> str:
+    """Compiles oracle.c into liboracle.so with gcc (-O2, IEEE semantics, OpenMP)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build(force=False)
+    L = ctypes.CDLL(_SO)
+    L.orc_tree_new.restype = ctypes.c_void_p
+    L.orc_tree_new.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int64,
+                               _i32p, _dp, _dp, ctypes.c_char_p, ctypes.c_int]
+    L.orc_tree_free.argtypes = [ctypes.c_void_p]
+    L.orc_tree_n_nodes.restype = ctypes.c_int64
+    L.orc_tree_n_nodes.argtypes = [ctypes.c_void_p]
+    L.orc_sh_basis.argtypes = [ctypes.c_int, _dp, _dp]
+    L.orc_ray_segments.restype = ctypes.c_int64
+    L.orc_ray_segments.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_int64, _dp, _dp, _i64p]
+    L.orc_render_rays.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp, _dp, _dp, ctypes.c_double,
+                                  _dp, _dp, _i64p, _dp]
+    L.orc_camera_rays.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, _dp, _dp]
+    L.orc_render_camera.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp,
+                                    ctypes.c_double, _dp, _dp, _i64p]
+    L.orc_grad.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp, _dp, _dp, ctypes.c_double, _dp,
+                           _dp, _dp]
+    L.orc_num_threads.restype = ctypes.c_int
+    L.orc_set_num_threads.argtypes = [ctypes.c_int]
+    _lib = L
+    return L
+
+
+def _d(a):
+    """Contiguous float64 copy (exact promotion from float32 / float16)."""
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _p(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+def num_threads() -> int:
+    return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    _load().orc_set_num_threads(int(n))
+
+
+def sh_basis(lmax: int, dirs) -> np.ndarray:
+    """Real SH values, (n, (lmax+1)^2), at the (normalised) directions dirs (n, 3)."""
+    L = _load()
+    d = _d(dirs).reshape(-1, 3)
+    K = (lmax + 1) ** 2
+    out = np.zeros((d.shape[0], K), np.float64)
+    for i in range(d.shape[0]):
+        L.orc_sh_basis(lmax, _p(d[i]), _p(out[i]))
+    return out
+
+
+def camera_rays(c2w, W, H, fx, fy, cx, cy):
+    """Pixel-centre pinhole rays (origins, directions), each (H*W, 3) float64."""
+    L = _load()
+    c = _d(c2w).reshape(12)
+    o = np.zeros((W * H, 3), np.float64)
+    d = np.zeros((W * H, 3), np.float64)
+    L.orc_camera_rays(_p(c), int(W), int(H), float(fx), float(fy), float(cx), float(cy), _p(o), _p(d))
+    return o, d
+
+
+class OracleTree:
+    """The oracle's own octree, built from a list of leaf cells.
+
+    cells: (n, 4) int (level, i, j, k); sigma: (n,) raw densities;
+    sh: (n, 3, K) coefficients, K = (lmax+1)^2, channel-major.
+    Values are promoted exactly to float64.
+    """
+
+    def __init__(self, depth, lmax, center, half, cells, sigma, sh):
+        L = _load()
+        self.depth, self.lmax = int(depth), int(lmax)
+        self.K = (self.lmax + 1) ** 2
+        cells = np.ascontiguousarray(np.asarray(cells, np.int32).reshape(-1, 4))
+        n = cells.shape[0]
+        sig = _d(sigma).reshape(n)
+        shv = _d(sh).reshape(n, 3, self.K)
+        ctr = _d(center).reshape(3)
+        err = ctypes.create_string_buffer(256)
+        h = L.orc_tree_new(self.depth, self.lmax, _p(ctr), float(half), n, _p(cells, _i32p),
+                           _p(sig), _p(shv), err, 256)
+        if not h:
+            raise ValueError("oracle tree: " + err.value.decode())
+        self._h = ctypes.c_void_p(h)
+        self.n_leaves = n
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc_tree_free(h)
+            self._h = None
+
+    @property
+    def n_nodes(self) -> int:
+        return _load().orc_tree_n_nodes(self._h)
+
+    def render_rays(self, o, d, bg=(1.0, 1.0, 1.0), gamma=0.0):
+        """Returns (rgb (n,3), T (n,), n_samples (n,), max clamped sigma met (n,))."""
+        L = _load()
+        o = _d(o).reshape(-1, 3)
+        d = _d(d).reshape(-1, 3)
+        n = o.shape[0]
+        rgb = np.zeros((n, 3), np.float64)
+        T = np.zeros(n, np.float64)
+        ns = np.zeros(n, np.int64)
+        sm = np.zeros(n, np.float64)
+        L.orc_render_rays(self._h, n, _p(o), _p(d), _p(_d(bg)), float(gamma), _p(rgb), _p(T),
+                          _p(ns, _i64p), _p(sm))
+        return rgb, T, ns, sm
+
+    def render_camera(self, c2w, W, H, fx, fy, cx, cy, bg=(1.0, 1.0, 1.0), gamma=0.0):
+        """Returns (rgb (H,W,3), T (H,W), n_samples (H,W))."""
+        L = _load()
+        rgb = np.zeros((H, W, 3), np.float64)
+        T = np.zeros((H, W), np.float64)
+        ns = np.zeros((H, W), np.int64)
+        L.orc_render_camera(self._h, _p(_d(c2w).reshape(12)), int(W), int(H), float(fx), float(fy),
+                            float(cx), float(cy), _p(_d(bg)), float(gamma), _p(rgb), _p(T),
+                            _p(ns, _i64p))
+        return rgb, T, ns
+
+    def grad(self, o, d, g, bg=(1.0, 1.0, 1.0), gamma=0.0):
+        """dL/dsigma_raw (n_leaves,) and dL/dsh (n_leaves, 3, K) for upstream g = dL/dC (n, 3)."""
+        L = _load()
+        o = _d(o).reshape(-1, 3)
+        d = _d(d).reshape(-1, 3)
+        g = _d(g).reshape(-1, 3)
+        gs = np.zeros(self.n_leaves, np.float64)
+        gsh = np.zeros((self.n_leaves, 3, self.K), np.float64)
+        L.orc_grad(self._h, o.shape[0], _p(o), _p(d), _p(_d(bg)), float(gamma), _p(g), _p(gs), _p(gsh))
+        return gs, gsh
+
+    def segments(self, o, d, cap=1 << 16):
+        """Segments of one ray: (a (m,), b (m,), leaf (m,)); leaf -1 is empty space."""
+        L = _load()
+        a = np.zeros(cap, np.float64)
+        b = np.zeros(cap, np.float64)
+        lf = np.zeros(cap, np.int64)
+        m = L.orc_ray_segments(self._h, _p(_d(o).reshape(3)), _p(_d(d).reshape(3)), cap, _p(a), _p(b),
+                               _p(lf, _i64p))
+        m = min(m, cap)
+        return a[:m], b[:m], lf[:m]

@@ -1,0 +1,512 @@
+/*
+ * oracle.c -- plain FP64 CPU reference ("the oracle") for PlenOctree volume
+ * rendering and its analytic derivatives.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is used by the test-suite, by the smoke
+ * check and by the CPU-baseline leg of the benchmark.  The product library
+ * (paper_2103_14024_amd/csrc) never includes, links or calls it, and it shares
+ * no code, header, table or helper with that library.
+ *
+ * What it computes (PlenOctrees, Yu et al. 2021, arXiv 2103.14024):
+ *   - a sparse octree whose leaves hold a raw density and, per RGB channel, a
+ *     vector of real spherical-harmonic coefficients (Sec. 4.2, "Sampling");
+ *   - for a ray, the exact sequence of segments between voxel boundaries
+ *     (Sec. 4.2, "Rendering"), found here by recursive subdivision of the box:
+ *     every child box is slab-clipped to the parent's interval and the
+ *     surviving children are visited in order of entry;
+ *   - the colour of each segment, the sigmoid of the SH expansion evaluated in
+ *     the ray direction (Sec. 4.1, NeRF-SH colour equation; the SH are built
+ *     from the complex definition of App. B.1 with the general
+ *     associated-Legendre recurrence, not from a table of polynomials);
+ *   - front-to-back piecewise-constant compositing (Sec. 3, eqn:quad) with the
+ *     background term and weights of App. B.3 ("Definitions"), the density
+ *     clamped at zero (App. B.3, last paragraph) and early stopping once the
+ *     transmittance falls below a threshold (Sec. 4.2, "Rendering");
+ *   - the colour and density derivatives of App. B.3, evaluated with the
+ *     two-pass scheme of the Remark there: the first pass yields the full
+ *     colour, the second subtracts a running prefix.
+ *
+ * Readings where the paper is silent (each is also listed in the design notes):
+ *   - SH: P_l^m includes the Condon-Shortley phase; the argument of the basis
+ *     is the unit propagation direction of the ray; theta is measured from +z,
+ *     phi = atan2(y, x); coefficient index k = l*l + l + m.
+ *   - Early stop: tested after every data segment with a strict "<"; the
+ *     background is then added with the remaining transmittance.
+ *   - A ray lying exactly in a plane of the grid (direction component 0)
+ *     belongs to the half-open cell [lo, hi) on that axis.
+ *   - Camera: pinhole, pixel centres, OpenGL camera frame (-z forward, +y up),
+ *     camera-to-world matrix row-major 3x4.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Tree                                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* A node of the oracle's own pointer octree.  child[c] = -1 means the child
+ * box is empty space; leaf >= 0 marks a data leaf (then it has no children).
+ * The oracle numbers the eight children as c = xbit + 2*ybit + 4*zbit. */
+typedef struct {
+    int32_t child[8];
+    int64_t leaf;
+} orc_node;
+
+typedef struct {
+    int depth;
+    int lmax;
+    int ncoef;              /* (lmax+1)^2 */
+    double center[3];
+    double half;
+    orc_node* nodes;
+    int64_t n_nodes, cap;
+    int64_t n_leaves;
+    double* sigma;          /* [leaf]            raw density before clamping */
+    double* sh;             /* [leaf][3][ncoef]  per-channel SH coefficients */
+} orc_tree;
+
+static int32_t new_node(orc_tree* t) {
+    if (t->n_nodes == t->cap) {
+        int64_t nc = t->cap ? 2 * t->cap : 1024;
+        orc_node* nn = (orc_node*)realloc(t->nodes, (size_t)nc * sizeof(orc_node));
+        if (!nn) return -1;
+        t->nodes = nn;
+        t->cap = nc;
+    }
+    orc_node* n = &t->nodes[t->n_nodes];
+    for (int c = 0; c < 8; ++c) n->child[c] = -1;
+    n->leaf = -1;
+    return (int32_t)(t->n_nodes++);
+}
+
+void orc_tree_free(orc_tree* t) {
+    if (!t) return;
+    free(t->nodes);
+    free(t->sigma);
+    free(t->sh);
+    free(t);
+}
+
+/* Builds the tree from a list of leaf cells.  cells[4*i .. 4*i+3] holds
+ * (level, i, j, k): the cell of edge 2*half / 2^level whose integer
+ * coordinates at that level are (i, j, k).  Cell i carries sigma[i] and
+ * sh[i*3*ncoef ..].  Cells must not overlap.  Returns NULL and writes a message
+ * into err on bad input. */
+orc_tree* orc_tree_new(int depth, int lmax, const double* center, double half,
+                       int64_t n_cells, const int32_t* cells,
+                       const double* sigma, const double* sh,
+                       char* err, int errlen) {
+    if (depth < 0 || depth > 20 || lmax < 0 || lmax > 8 || !(half > 0)) {
+        snprintf(err, errlen, "bad tree description");
+        return NULL;
+    }
+    orc_tree* t = (orc_tree*)calloc(1, sizeof(orc_tree));
+    t->depth = depth;
+    t->lmax = lmax;
+    t->ncoef = (lmax + 1) * (lmax + 1);
+    for (int a = 0; a < 3; ++a) t->center[a] = center[a];
+    t->half = half;
+    t->n_leaves = n_cells;
+    size_t per = (size_t)3 * t->ncoef;
+    t->sigma = (double*)malloc(sizeof(double) * (size_t)(n_cells ? n_cells : 1));
+    t->sh = (double*)malloc(sizeof(double) * per * (size_t)(n_cells ? n_cells : 1));
+    if (n_cells) {
+        memcpy(t->sigma, sigma, sizeof(double) * (size_t)n_cells);
+        memcpy(t->sh, sh, sizeof(double) * per * (size_t)n_cells);
+    }
+    new_node(t); /* root */
+    for (int64_t q = 0; q < n_cells; ++q) {
+        int level = cells[4 * q + 0];
+        int64_t ci = cells[4 * q + 1], cj = cells[4 * q + 2], ck = cells[4 * q + 3];
+        if (level < 0 || level > depth || ci < 0 || cj < 0 || ck < 0 ||
+            ci >= (1LL << level) || cj >= (1LL << level) || ck >= (1LL << level)) {
+            snprintf(err, errlen, "cell %lld out of range", (long long)q);
+            orc_tree_free(t);
+            return NULL;
+        }
+        int32_t cur = 0;
+        for (int s = 0; s < level; ++s) {
+            if (t->nodes[cur].leaf >= 0) {
+                snprintf(err, errlen, "cell %lld lies inside another leaf", (long long)q);
+                orc_tree_free(t);
+                return NULL;
+            }
+            int sh_ = level - 1 - s;
+            int c = (int)(((ci >> sh_) & 1) + 2 * ((cj >> sh_) & 1) + 4 * ((ck >> sh_) & 1));
+            int32_t nx = t->nodes[cur].child[c];
+            if (nx < 0) {
+                nx = new_node(t);
+                if (nx < 0) {
+                    snprintf(err, errlen, "out of memory");
+                    orc_tree_free(t);
+                    return NULL;
+                }
+                t->nodes[cur].child[c] = nx;
+            }
+            cur = nx;
+        }
+        int has_child = 0;
+        for (int c = 0; c < 8; ++c) has_child |= (t->nodes[cur].child[c] >= 0);
+        if (t->nodes[cur].leaf >= 0 || has_child) {
+            snprintf(err, errlen, "cell %lld overlaps another cell", (long long)q);
+            orc_tree_free(t);
+            return NULL;
+        }
+        t->nodes[cur].leaf = q;
+    }
+    return t;
+}
+
+int64_t orc_tree_n_nodes(const orc_tree* t) { return t->n_nodes; }
+
+/* ------------------------------------------------------------------------ */
+/* Real spherical harmonics from the complex definition (App. B.1)           */
+/* ------------------------------------------------------------------------ */
+
+static double factorial(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+
+/* Associated Legendre function P_l^m(x), m >= 0, with the Condon-Shortley
+ * phase (-1)^m, by the standard recurrences in l. */
+static double assoc_legendre(int l, int m, double x) {
+    double pmm = 1.0;
+    double s = sqrt(fmax(0.0, (1.0 - x) * (1.0 + x)));
+    for (int i = 1; i <= m; ++i) pmm *= -(2.0 * i - 1.0) * s; /* (-1)^m (2m-1)!! s^m */
+    if (l == m) return pmm;
+    double pm1 = x * (2.0 * m + 1.0) * pmm;                   /* P_{m+1}^m */
+    if (l == m + 1) return pm1;
+    double p2 = 0.0;
+    for (int ll = m + 2; ll <= l; ++ll) {
+        p2 = ((2.0 * ll - 1.0) * x * pm1 - (ll + m - 1.0) * pmm) / (double)(ll - m);
+        pmm = pm1;
+        pm1 = p2;
+    }
+    return p2;
+}
+
+/* Writes the (lmax+1)^2 real SH values at direction d (normalised here) into
+ * out, index l*l + l + m. */
+void orc_sh_basis(int lmax, const double* d_in, double* out) {
+    double n = sqrt(d_in[0] * d_in[0] + d_in[1] * d_in[1] + d_in[2] * d_in[2]);
+    double x = d_in[0] / n, y = d_in[1] / n, z = d_in[2] / n;
+    double cos_theta = z;
+    double phi = atan2(y, x);
+    for (int l = 0; l <= lmax; ++l) {
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double norm = sqrt((2.0 * l + 1.0) / (4.0 * ORC_PI) * factorial(l - am) / factorial(l + am));
+            double p = assoc_legendre(l, am, cos_theta);
+            /* complex Y_l^{|m|} = norm * p * exp(i |m| phi) */
+            double re = norm * p * cos(am * phi);
+            double im = norm * p * sin(am * phi);
+            double sign = (am % 2) ? -1.0 : 1.0; /* (-1)^m */
+            double v;
+            if (m < 0) v = sqrt(2.0) * sign * im;
+            else if (m == 0) v = norm * p;
+            else v = sqrt(2.0) * sign * re;
+            out[l * l + l + m] = v;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Segments by recursive subdivision (Sec. 4.2, "Rendering")                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double a, b;   /* ray parameter interval, unit direction */
+    int64_t leaf;  /* data leaf id, or -1 for empty space */
+} orc_seg;
+
+typedef struct {
+    orc_seg* s;
+    int64_t n, cap;
+} seglist;
+
+static void push_seg(seglist* L, double a, double b, int64_t leaf) {
+    if (L->n == L->cap) {
+        L->cap = L->cap ? 2 * L->cap : 64;
+        L->s = (orc_seg*)realloc(L->s, (size_t)L->cap * sizeof(orc_seg));
+    }
+    L->s[L->n].a = a;
+    L->s[L->n].b = b;
+    L->s[L->n].leaf = leaf;
+    L->n++;
+}
+
+/* Interval of t where o + t d lies in the box [lo, hi).  A zero direction
+ * component keeps the whole line if lo <= o < hi on that axis, else nothing. */
+static void slab(const double* o, const double* d, const double* lo, const double* hi,
+                 double* ta, double* tb) {
+    double a = -INFINITY, b = INFINITY;
+    for (int k = 0; k < 3; ++k) {
+        if (d[k] == 0.0) {
+            if (!(lo[k] <= o[k] && o[k] < hi[k])) {
+                *ta = INFINITY;
+                *tb = -INFINITY;
+                return;
+            }
+        } else {
+            double t1 = (lo[k] - o[k]) / d[k];
+            double t2 = (hi[k] - o[k]) / d[k];
+            if (t1 > t2) { double s = t1; t1 = t2; t2 = s; }
+            if (t1 > a) a = t1;
+            if (t2 < b) b = t2;
+        }
+    }
+    *ta = a;
+    *tb = b;
+}
+
+static void visit(const orc_tree* t, int32_t node, const double* lo, double size,
+                  double a, double b, const double* o, const double* d, seglist* out) {
+    const orc_node* n = &t->nodes[node];
+    if (n->leaf >= 0) {
+        push_seg(out, a, b, n->leaf);
+        return;
+    }
+    double hs = size * 0.5;
+    double ka[8], kb[8], klo[8][3];
+    int kc[8], nk = 0;
+    for (int c = 0; c < 8; ++c) {
+        double clo[3] = {lo[0] + (c & 1) * hs, lo[1] + ((c >> 1) & 1) * hs, lo[2] + ((c >> 2) & 1) * hs};
+        double chi[3] = {clo[0] + hs, clo[1] + hs, clo[2] + hs};
+        double ca, cb;
+        slab(o, d, clo, chi, &ca, &cb);
+        if (ca < a) ca = a;
+        if (cb > b) cb = b;
+        if (cb - ca > 0.0) {
+            /* insertion into the list sorted by entry parameter */
+            int p = nk++;
+            while (p > 0 && ka[p - 1] > ca) {
+                ka[p] = ka[p - 1]; kb[p] = kb[p - 1]; kc[p] = kc[p - 1];
+                memcpy(klo[p], klo[p - 1], sizeof klo[p]);
+                --p;
+            }
+            ka[p] = ca; kb[p] = cb; kc[p] = c;
+            memcpy(klo[p], clo, sizeof clo);
+        }
+    }
+    for (int q = 0; q < nk; ++q) {
+        int32_t ch = n->child[kc[q]];
+        if (ch < 0) push_seg(out, ka[q], kb[q], -1);
+        else visit(t, ch, klo[q], hs, ka[q], kb[q], o, d, out);
+    }
+}
+
+/* Segments of the ray o + t d (d normalised here), t >= 0, through the box. */
+static void ray_segments(const orc_tree* t, const double* o, const double* d_in, double* dn,
+                         seglist* out) {
+    double n = sqrt(d_in[0] * d_in[0] + d_in[1] * d_in[1] + d_in[2] * d_in[2]);
+    for (int k = 0; k < 3; ++k) dn[k] = d_in[k] / n;
+    out->n = 0;
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = t->center[k] - t->half;
+        hi[k] = t->center[k] + t->half;
+    }
+    double a, b;
+    slab(o, dn, lo, hi, &a, &b);
+    if (a < 0.0) a = 0.0;
+    if (b - a > 0.0) visit(t, 0, lo, 2.0 * t->half, a, b, o, dn, out);
+}
+
+/* Public: list the segments of one ray (for tests).  Returns the number of
+ * segments; at most cap are written. */
+int64_t orc_ray_segments(const orc_tree* t, const double* o, const double* d, int64_t cap,
+                         double* seg_a, double* seg_b, int64_t* seg_leaf) {
+    seglist L = {0};
+    double dn[3];
+    ray_segments(t, o, d, dn, &L);
+    for (int64_t i = 0; i < L.n && i < cap; ++i) {
+        seg_a[i] = L.s[i].a;
+        seg_b[i] = L.s[i].b;
+        seg_leaf[i] = L.s[i].leaf;
+    }
+    int64_t n = L.n;
+    free(L.s);
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Compositing (Sec. 3 eqn:quad; App. B.3)                                   */
+/* ------------------------------------------------------------------------ */
+
+static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* Colour of a data leaf seen along direction with basis Y. */
+static void leaf_colour(const orc_tree* t, int64_t leaf, const double* Y, double* c) {
+    const double* k = t->sh + (size_t)leaf * 3 * t->ncoef;
+    for (int ch = 0; ch < 3; ++ch) {
+        double z = 0.0;
+        for (int i = 0; i < t->ncoef; ++i) z += k[ch * t->ncoef + i] * Y[i];
+        c[ch] = sigmoid(z);
+    }
+}
+
+/* Renders one ray.  Returns colour, final transmittance, number of data
+ * samples composited and the largest clamped density met. */
+static void render_one(const orc_tree* t, const double* o, const double* d, const double* bg,
+                       double gamma, seglist* L, double* Y, double* rgb, double* T_out,
+                       int64_t* ns_out, double* smax_out) {
+    double dn[3];
+    ray_segments(t, o, d, dn, L);
+    orc_sh_basis(t->lmax, dn, Y);
+    double C[3] = {0, 0, 0}, T = 1.0, smax = 0.0;
+    int64_t ns = 0;
+    for (int64_t i = 0; i < L->n; ++i) {
+        int64_t leaf = L->s[i].leaf;
+        if (leaf < 0) continue;                 /* empty space: sigma = 0 */
+        double sig = fmax(t->sigma[leaf], 0.0);  /* sigma = max(raw, 0) */
+        double delta = L->s[i].b - L->s[i].a;
+        double tau = sig * delta;
+        double alpha = -expm1(-tau);             /* 1 - exp(-sigma delta) */
+        double c[3];
+        leaf_colour(t, leaf, Y, c);
+        for (int ch = 0; ch < 3; ++ch) C[ch] += T * alpha * c[ch];
+        T *= exp(-tau);
+        ++ns;
+        if (sig > smax) smax = sig;
+        if (T < gamma) break;
+    }
+    for (int ch = 0; ch < 3; ++ch) rgb[ch] = C[ch] + T * bg[ch];
+    *T_out = T;
+    *ns_out = ns;
+    *smax_out = smax;
+}
+
+/* Renders n rays (o, d: n x 3).  Any of T_out, ns_out, smax_out may be NULL.
+ * Uses OpenMP threads over rays when built with -fopenmp. */
+void orc_render_rays(const orc_tree* t, int64_t n, const double* o, const double* d,
+                     const double* bg, double gamma, double* rgb, double* T_out,
+                     int64_t* ns_out, double* smax_out) {
+#pragma omp parallel
+    {
+        seglist L = {0};
+        double Y[81];
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t r = 0; r < n; ++r) {
+            double T, smax;
+            int64_t ns;
+            render_one(t, o + 3 * r, d + 3 * r, bg, gamma, &L, Y, rgb + 3 * r, &T, &ns, &smax);
+            if (T_out) T_out[r] = T;
+            if (ns_out) ns_out[r] = ns;
+            if (smax_out) smax_out[r] = smax;
+        }
+        free(L.s);
+    }
+}
+
+/* Pinhole camera rays for the pixel centres of a W x H image, row-major
+ * (row v, column u).  c2w is the row-major 3x4 camera-to-world matrix whose
+ * first three columns are the camera's x (right), y (up) and z (backward)
+ * axes; the camera looks along -z. */
+void orc_camera_rays(const double* c2w, int W, int H, double fx, double fy, double cx,
+                     double cy, double* o, double* d) {
+    for (int v = 0; v < H; ++v) {
+        for (int u = 0; u < W; ++u) {
+            double x = (u + 0.5 - cx) / fx;
+            double y = -(v + 0.5 - cy) / fy;
+            double z = -1.0;
+            int64_t p = (int64_t)v * W + u;
+            for (int r = 0; r < 3; ++r) {
+                d[3 * p + r] = c2w[4 * r + 0] * x + c2w[4 * r + 1] * y + c2w[4 * r + 2] * z;
+                o[3 * p + r] = c2w[4 * r + 3];
+            }
+        }
+    }
+}
+
+/* Renders a camera image into rgb (H x W x 3).  T_out / ns_out may be NULL. */
+void orc_render_camera(const orc_tree* t, const double* c2w, int W, int H, double fx,
+                       double fy, double cx, double cy, const double* bg, double gamma,
+                       double* rgb, double* T_out, int64_t* ns_out) {
+    int64_t n = (int64_t)W * H;
+    double* o = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* d = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    orc_camera_rays(c2w, W, H, fx, fy, cx, cy, o, d);
+    orc_render_rays(t, n, o, d, bg, gamma, rgb, T_out, ns_out, NULL);
+    free(o);
+    free(d);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gradients (App. B.3, derivation and Remark)                               */
+/* ------------------------------------------------------------------------ */
+
+/* Accumulates dL/dsigma_raw (n_leaves) and dL/dsh (n_leaves x 3 x ncoef) for
+ * rays (o, d) with upstream gradient g = dL/dC (n x 3).  Single-threaded.
+ * Pass 1 renders the ray to get C = sum_k w_k c_k (background included);
+ * pass 2 walks the same segments again, keeping the prefix P_i of w_k c_k:
+ *   dC/dsigma_i = delta_i (c_i T_{i+1} - (C - P_i)), zero where raw <= 0,
+ *   dC/dc_i = w_i, and through the sigmoid dc/dz = c (1 - c), dz/dk = Y. */
+void orc_grad(const orc_tree* t, int64_t n, const double* o, const double* d,
+              const double* bg, double gamma, const double* g, double* grad_sigma,
+              double* grad_sh) {
+    seglist L = {0};
+    double Y[81];
+    int K = t->ncoef;
+    for (int64_t r = 0; r < n; ++r) {
+        double C[3], Tf, smax;
+        int64_t ns;
+        render_one(t, o + 3 * r, d + 3 * r, bg, gamma, &L, Y, C, &Tf, &ns, &smax);
+        /* L and Y still hold this ray's segments and basis. */
+        const double* gr = g + 3 * r;
+        double P[3] = {0, 0, 0}, T = 1.0;
+        int64_t done = 0;
+        for (int64_t i = 0; i < L.n && done < ns; ++i) {
+            int64_t leaf = L.s[i].leaf;
+            if (leaf < 0) continue;
+            ++done;
+            double raw = t->sigma[leaf];
+            double sig = fmax(raw, 0.0);
+            double delta = L.s[i].b - L.s[i].a;
+            double tau = sig * delta;
+            double alpha = -expm1(-tau);
+            double Tn = T * exp(-tau);
+            double w = T * alpha;
+            double c[3];
+            leaf_colour(t, leaf, Y, c);
+            double gs = 0.0;
+            for (int ch = 0; ch < 3; ++ch) {
+                P[ch] += w * c[ch];
+                double dCds = delta * (c[ch] * Tn - (C[ch] - P[ch]));
+                gs += gr[ch] * dCds;
+                double gz = gr[ch] * w * c[ch] * (1.0 - c[ch]);
+                double* gk = grad_sh + ((size_t)leaf * 3 + ch) * K;
+                for (int q = 0; q < K; ++q) gk[q] += gz * Y[q];
+            }
+            if (raw > 0.0) grad_sigma[leaf] += gs;
+            T = Tn;
+        }
+    }
+    free(L.s);
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
