@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Benchmark of the PlenOctree renderer on one MI355X.
+
+Workload: the depth-9 Gaussian-blob surface-band tree (~2.9M leaves, SH
+degree 3, sigma ~ lognormal(2, 1), SH ~ N(0, 0.5^2)), 200 camera poses
+area-uniform on the upper hemisphere at radius 4 looking at the origin,
+800x800 pixels, 40 degree horizontal field of view, white background, early
+stop at T < 1e-4.  A step is one 800x800 frame: one kernel launch over all
+640,000 rays.  Inputs are resident in HBM before timing; the image stays on
+the device.
+
+Prints one JSON line: FPS of the float32 tree (headline value), Msamples/s,
+the float16-leaf form, a roofline entry for the render kernel and the FP64
+oracle's throughput on the host cores as the CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "800x800 FPS + Msamples/s, fp32 vs fp16 leaves; served p50/p99 ms; HBM GB/s"
+HBM_PEAK_GBPS = 8000.0
+W = H = 800
+N_POSES = 200
+STOP_T = 1e-4
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def record_bytes(tree) -> int:
+    """Bytes one sample gathers: the density plus the 3K SH coefficients."""
+    es = 4 if tree.dtype == 0 else 2
+    return es * (1 + 3 * tree.K)
+
+
+def measure(po, tree, cams, steps, warmup, stream):
+    import torch
+
+    img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    # per-pose samples and traversal steps, outside the timed region
+    aux = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    samples, tsteps = [], []
+    for cam in cams:
+        po.render_camera(tree, cam, stop_T=STOP_T, aux=True, out=img, aux_out=aux, stream=stream)
+        a = aux.view(-1, 3).sum(0).cpu()
+        samples.append(float(a[1]))
+        tsteps.append(float(a[2]))
+    for i in range(warmup):
+        po.render_camera(tree, cams[i % len(cams)], stop_T=STOP_T, out=img, stream=stream)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        t0.record(stream)
+        for i in range(steps):
+            po.render_camera(tree, cams[i % len(cams)], stop_T=STOP_T, out=img, stream=stream)
+        t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    n_samples = sum(samples[i % len(cams)] for i in range(steps))
+    n_steps = sum(tsteps[i % len(cams)] for i in range(steps))
+    rays = steps * W * H
+    alg_bytes = n_samples * record_bytes(tree) + rays * 12
+    return dict(ms=ms, ms_per_step=ms / steps, fps=steps / (ms * 1e-3), msamples_per_s=n_samples / (ms * 1e3),
+                mrays_per_s=rays / (ms * 1e3), samples_per_ray=n_samples / rays, steps_per_ray=n_steps / rays,
+                alg_gbps=alg_bytes / (ms * 1e-3) / 1e9, alg_bytes_per_launch=alg_bytes / steps)
+
+
+def cpu_baseline(scene, pose, budget_s=12.0):
+    """The FP64 oracle on the host cores, on a bounded random sample of the
+    rays of one frame; scaled to frames per second."""
+    import numpy as np
+
+    import oracle
+    from paper_2103_14024_amd import scenes
+
+    t = oracle.OracleTree(scene["depth"], scene["sh_degree"], scene["center"], scene["half"], scene["cells"],
+                          scene["sigma"], scene["sh"])
+    fx, fy, cx, cy = scenes.intrinsics(W, H, 40.0)
+    o, d = oracle.camera_rays(pose, W, H, fx, fy, cx, cy)
+    rng = np.random.default_rng(0)
+    idx = rng.permutation(W * H)
+    n0 = 4000
+    t0 = time.perf_counter()
+    t.render_rays(o[idx[:n0]], d[idx[:n0]], gamma=STOP_T)
+    dt0 = time.perf_counter() - t0
+    n1 = int(min(W * H - n0, max(0, budget_s / max(dt0, 1e-6) * n0 - n0)))
+    t1 = time.perf_counter()
+    if n1 > 0:
+        t.render_rays(o[idx[n0:n0 + n1]], d[idx[n0:n0 + n1]], gamma=STOP_T)
+    dt1 = time.perf_counter() - t1
+    n, dt = n0 + n1, dt0 + dt1
+    rays_per_s = n / dt
+    return {"value": rays_per_s / (W * H), "unit": "FPS", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n} random pixels of one 800x800 frame of the same scene ({dt:.1f} s), FP64, "
+                      f"{rays_per_s / 1e3:.1f} krays/s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the renderer needs no communication and this build runs on a "
+              "single MI355X; rerun with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2103_14024_amd as po
+    from paper_2103_14024_amd import scenes
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    scene = scenes.scene_blobs()
+    log(f"scene: {len(scene['cells'])} leaves in {time.perf_counter() - t0:.1f} s")
+    poses = scenes.hemisphere_poses(N_POSES, 4.0, 2)
+    fx, fy, cx, cy = scenes.intrinsics(W, H, 40.0)
+    cams = [po.Camera(p, W, H, fx, fy, cx, cy) for p in poses]
+    stream = torch.cuda.current_stream()
+
+    tree32 = po.Tree.from_scene(scene, dtype="f32")
+    torch.cuda.synchronize()
+    log(f"fp32 tree: {tree32.n_nodes} nodes, {tree32.nbytes() / 1e6:.0f} MB")
+    r32 = measure(po, tree32, cams, args.steps, args.warmup, stream)
+    log(f"fp32: {r32['fps']:.1f} FPS, {r32['msamples_per_s']:.0f} Msamples/s, "
+        f"{r32['samples_per_ray']:.2f} samples/ray, {r32['steps_per_ray']:.1f} steps/ray")
+    out = {
+        "metric": METRIC, "value": round(r32["fps"], 2), "unit": "FPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r32["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "plenoctree-render depth-9 blob band, SH degree 3, 800x800, 200 hemisphere poses",
+                   "leaves": int(len(scene["cells"])), "nodes": int(tree32.n_nodes), "depth": 9, "sh_degree": 3,
+                   "width": W, "height": H, "poses": N_POSES, "stop_T": STOP_T, "leaf_dtype": "f32"},
+        "msamples_per_s": round(r32["msamples_per_s"], 1), "mrays_per_s": round(r32["mrays_per_s"], 1),
+        "samples_per_ray": round(r32["samples_per_ray"], 3), "steps_per_ray": round(r32["steps_per_ray"], 2),
+        "roofline": {"bound": "hbm", "achieved": round(r32["alg_gbps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(r32["alg_gbps"] / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "k_render_camera<float,16,16,48,1>",
+                     "alg_bytes_per_launch": int(r32["alg_bytes_per_launch"])},
+        "paper_context": {"fps": 167.68, "hardware": "Tesla V100", "workload": "NeRF-synthetic real scenes"},
+    }
+    del tree32
+    torch.cuda.empty_cache()
+    if not args.no_fp16:
+        tree16 = po.Tree.from_scene(scene, dtype="f16")
+        r16 = measure(po, tree16, cams, args.steps, args.warmup, stream)
+        log(f"fp16: {r16['fps']:.1f} FPS, {r16['msamples_per_s']:.0f} Msamples/s")
+        out["fp16"] = {"fps": round(r16["fps"], 2), "ms_per_step": round(r16["ms_per_step"], 4),
+                       "msamples_per_s": round(r16["msamples_per_s"], 1),
+                       "alg_gbps": round(r16["alg_gbps"], 1), "speedup_vs_fp32": round(r16["fps"] / r32["fps"], 3)}
+        del tree16
+    if not args.no_cpu_baseline:
+        log("cpu baseline (FP64 oracle)")
+        out["cpu_baseline"] = cpu_baseline(scene, poses[0])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * plenoctree.h -- C ABI of libplenoctree.so, an MI355X (gfx950) renderer for
+ * PlenOctrees (Yu et al., "PlenOctrees for Real-time Rendering of Neural
+ * Radiance Fields", ICCV 2021, arXiv 2103.14024).
+ *
+ * A PlenOctree is a sparse octree over an axis-aligned box whose data leaves
+ * hold a raw density and, for each RGB channel, a vector of real spherical
+ * harmonic (SH) coefficients (Sec. 4.2, "Sampling"; SH of App. B.1).  A ray
+ * is cut into the exact segments between voxel boundaries, large empty voxels
+ * being crossed in one step (Sec. 4.2, "Rendering"); each data segment
+ * contributes with the piecewise-constant quadrature of Sec. 3 (eqn:quad) and
+ * the background term of App. B.3; marching stops early once the
+ * transmittance falls below a threshold (Sec. 4.2, "Rendering").  The
+ * gradient entry point implements the analytic derivatives of App. B.3 for
+ * the direct optimisation of Sec. 4.3.
+ *
+ * General conventions
+ *  - Every function returns a po_status.  On any code other than PO_OK the
+ *    call has written no output and queued no GPU work; po_last_error()
+ *    returns a message for the calling thread.  No C++ exception crosses the
+ *    ABI.
+ *  - "d_" pointers are device pointers (HBM of the current HIP device),
+ *    "h_" / plain pointers are host pointers.  The caller owns every buffer.
+ *    A po_tree handle owns only its metadata and borrows the device arrays
+ *    given to po_tree_bind; they must outlive all work queued with it.
+ *  - Render calls only enqueue work on `stream` (a hipStream_t; NULL is the
+ *    null stream) and return; outputs are valid once the stream has
+ *    completed.  Handles are immutable after bind, so renders of one tree on
+ *    several streams may run concurrently.
+ *  - n == 0 (no rays) is a no-op returning PO_OK.
+ *
+ * Geometry
+ *  - The tree box is [center - half_size, center + half_size]^3 in world
+ *    units.  Level 0 is the box; a cell at level L has edge
+ *    2*half_size / 2^L and integer coordinates (i, j, k) in [0, 2^L)^3.
+ *  - Child array: int32 child[n_nodes][8]; node 0 is the root.  The child
+ *    slot of a cell is 4*xbit + 2*ybit + zbit (bits of the child's integer
+ *    coordinates).  Entry e > 0: internal node e.  e == 0: empty space
+ *    (density 0, no record).  e < 0: data leaf number -e-1.
+ *  - Leaf records: sigma[n_leaves] (raw density; the renderer uses
+ *    max(sigma, 0), App. B.3 last paragraph) and sh[n_leaves][sh_stride],
+ *    whose first 3*K elements are channel-major coefficients
+ *    sh[leaf][c*K + l*l + l + m], K = (sh_degree+1)^2 (Sec. 4.1).  Both
+ *    arrays are float32 (PO_F32) or IEEE binary16 (PO_F16); FP16 values are
+ *    widened to float32 and all arithmetic is float32.
+ *  - Rays: origins o and directions d, float32 [n][3]; d need not be unit
+ *    length (it is normalised; segment lengths are world units along the
+ *    unit direction).  A ray starts at t = 0 (origins inside the box render
+ *    from the origin).  The SH basis is evaluated at the unit direction of
+ *    propagation.
+ *  - Camera: pinhole through pixel centres; pixel (row v, column u) looks
+ *    along R * ((u + 0.5 - cx)/fx, -(v + 0.5 - cy)/fy, -1), R the first three
+ *    columns of the row-major 3x4 camera-to-world matrix c2w whose last
+ *    column is the camera position (OpenGL frame: -z forward, +y up).
+ *    Images are row-major [height][width][3] float32.
+ */
+#ifndef PLENOCTREE_H
+#define PLENOCTREE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PO_MAX_DEPTH 15
+#define PO_MAX_SH_DEGREE 3
+#define PO_BATCH_MAX_JOBS 16
+#define PO_TILE 16 /* camera images are processed in 16 x 16 pixel tiles */
+
+typedef enum {
+    PO_OK = 0,
+    PO_ERR_INVALID = 1,     /* bad argument: NULL pointer, negative size, bad option, misalignment */
+    PO_ERR_TREE = 2,        /* malformed tree or cell list */
+    PO_ERR_OOM = 3,         /* host allocation failed */
+    PO_ERR_DEVICE = 4,      /* HIP runtime error */
+    PO_ERR_UNSUPPORTED = 5  /* valid but unsupported combination */
+} po_status;
+
+typedef enum { PO_F32 = 0, PO_F16 = 1 } po_dtype;
+
+/* Description of a tree.  sh_stride: elements from one leaf's SH record to
+ * the next; 0 means 3*K.  Must be >= 3*K, and sh_stride * element size must
+ * be a multiple of 4 bytes. */
+typedef struct {
+    int32_t depth;      /* maximum depth D, 1..PO_MAX_DEPTH */
+    int32_t sh_degree;  /* l_max, 0..PO_MAX_SH_DEGREE */
+    float center[3];
+    float half_size;    /* > 0 */
+    int32_t dtype;      /* po_dtype of sigma and sh */
+    int32_t sh_stride;
+} po_tree_desc;
+
+/* Per-call rendering options. */
+#define PO_OUT_AUX 1u /* also write aux[ray][3] = {final transmittance, data samples, traversal steps} */
+typedef struct {
+    float bg[3];        /* background colour c_N (App. B.3) */
+    float stop_T;       /* early stop once T < stop_T after a data segment (Sec. 4.2); 0 disables */
+    int32_t max_steps;  /* cap on traversal steps per ray; 0 = 3*2^D + 8, which valid trees never reach */
+    uint32_t flags;     /* PO_OUT_* */
+} po_render_opts;
+
+typedef struct {
+    float c2w[12];      /* row-major 3x4 camera-to-world */
+    int32_t width, height;
+    float fx, fy, cx, cy;
+} po_camera;
+
+typedef struct po_tree po_tree;       /* opaque, immutable after bind */
+typedef struct po_builder po_builder; /* opaque, host-side build state */
+
+/* ------------------------------------------------------------------ build
+ * Octree construction from leaf cells (Sec. 4.2, "Filtering": the surviving
+ * voxels become leaves, everything else is empty).  Host only, no GPU.
+ *
+ * po_builder_create: h_cells is [n_cells][4] int32 (level, i, j, k) with
+ * 1 <= level <= depth and coordinates in [0, 2^level).  Cells must not
+ * overlap.  Leaves are numbered in Morton order of their corner; internal
+ * nodes are numbered level by level (all nodes of level L before any of level
+ * L+1), Morton order within a level, so the top levels form a prefix of the
+ * child array.  Errors: PO_ERR_INVALID (NULL, n_cells < 0, bad desc),
+ * PO_ERR_TREE (cell out of range, overlapping or duplicate cells),
+ * PO_ERR_OOM. */
+po_status po_builder_create(const po_tree_desc* desc, int64_t n_cells, const int32_t* h_cells,
+                            po_builder** out);
+/* Sizes of the built tree: n_nodes (>= 1, the root always exists) and n_leaves (== n_cells). */
+po_status po_builder_sizes(const po_builder* b, int64_t* n_nodes, int64_t* n_leaves);
+/* Writes h_child[n_nodes][8] and h_leaf_perm[n_leaves]: leaf j of the tree is
+ * the caller's cell h_leaf_perm[j] (so sigma_tree[j] = sigma_cells[perm[j]]). */
+po_status po_builder_emit(const po_builder* b, int32_t* h_child, int64_t* h_leaf_perm);
+po_status po_builder_destroy(po_builder* b);
+
+/* Checks a host copy of a child array: every entry in range, every internal
+ * node referenced exactly once and reachable from the root (no cycles, no
+ * sharing), no internal node at depth D, and, when h_sigma is not NULL
+ * (dtype of desc, n_leaves values), every density finite.  PO_ERR_TREE with
+ * a message naming the first fault. */
+po_status po_tree_validate(const po_tree_desc* desc, int64_t n_nodes, const int32_t* h_child,
+                           int64_t n_leaves, const void* h_sigma);
+
+/* -------------------------------------------------------------------- bind
+ * Wraps device arrays (child, sigma, sh as described above) in a handle.  No
+ * data is copied or checked on the device; the kernels treat an out-of-range
+ * entry, or an internal node below depth D, as empty space and count it in
+ * the device error counter (po_device_errors), so a malformed array cannot
+ * make them read out of bounds.  d_sh must be aligned to 4 bytes (16 for the
+ * fastest loads).  Errors: PO_ERR_INVALID. */
+po_status po_tree_bind(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child,
+                       int64_t n_leaves, const void* d_sigma, const void* d_sh, po_tree** out);
+po_status po_tree_destroy(po_tree* t);
+
+/* ------------------------------------------------------------------ render
+ * po_render_rays: renders n rays into d_rgb[n][3]; with PO_OUT_AUX also
+ * d_aux[n][3].  The colour is sum_i T_i (1 - exp(-sigma_i delta_i)) c_i +
+ * T_N bg over the data segments met before the early stop (Sec. 3 eqn:quad,
+ * App. B.3), c_i = sigmoid(sum_k sh[leaf][ch][k] Y_k(d)) (Sec. 4.1).
+ * Errors: PO_ERR_INVALID (NULL tree/opts/arrays with n > 0, n < 0, bad
+ * options), PO_ERR_DEVICE (launch failure). */
+po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, const float* d_dirs,
+                         const po_render_opts* opts, float* d_rgb, float* d_aux, void* stream);
+
+/* po_render_camera: renders a camera image into d_rgb[height][width][3]
+ * (and d_aux[height][width][3] with PO_OUT_AUX).  width, height in
+ * [1, 16384]; fx, fy non-zero.  Errors as for po_render_rays. */
+po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_render_opts* opts,
+                           float* d_rgb, float* d_aux, void* stream);
+
+/* -------------------------------------------------------------- gradients
+ * Accumulates (+=) into d_grad_sigma[n_leaves] and d_grad_sh[n_leaves][sh_stride]
+ * the gradient of L with respect to the raw leaf values, given
+ * d_grad_rgb = dL/dC [n][3] and the colours d_rgb_fwd [n][3] that
+ * po_render_rays produced for the same rays and options (App. B.3: the first
+ * pass stores the full colour, this second pass walks the same segments and
+ * subtracts a running prefix; dC/dsigma_i = delta_i (c_i T_{i+1} - (C -
+ * P_i)), zero where the raw density is <= 0; dC/dc_i = w_i, then the chain
+ * rule through the sigmoid and the SH basis).  Several rays may hit one
+ * leaf, so accumulation uses float atomics and its summation order is not
+ * deterministic.  Zero the outputs first when a fresh gradient is wanted.
+ * Errors: PO_ERR_INVALID, PO_ERR_UNSUPPORTED (tree not PO_F32),
+ * PO_ERR_DEVICE. */
+po_status po_render_rays_backward(const po_tree* t, int64_t n, const float* d_origins,
+                                  const float* d_dirs, const po_render_opts* opts,
+                                  const float* d_rgb_fwd, const float* d_grad_rgb,
+                                  float* d_grad_sigma, float* d_grad_sh, void* stream);
+
+/* ---------------------------------------------------------------- batches
+ * One job renders the 16x16 tiles [tile_begin, tile_end) of one camera
+ * image of one tree (tiles numbered row-major over ceil(W/16) x ceil(H/16)).
+ * po_render_batch renders up to PO_BATCH_MAX_JOBS jobs, of any trees and
+ * image sizes, with as few kernel launches as their (dtype, SH degree)
+ * groups allow, all on `stream`.  Each job's pixels are computed exactly as
+ * po_render_camera computes them.  Errors: as po_render_camera, plus
+ * PO_ERR_INVALID for n_jobs outside [0, PO_BATCH_MAX_JOBS] or a tile range
+ * outside the image. */
+typedef struct {
+    const po_tree* tree;
+    po_camera cam;
+    po_render_opts opts;
+    float* d_rgb;       /* [height][width][3] */
+    float* d_aux;       /* [height][width][3] or NULL */
+    int32_t tile_begin, tile_end;
+} po_job;
+po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream);
+/* Number of 16x16 tiles of a camera image. */
+po_status po_camera_tiles(const po_camera* cam, int32_t* n_tiles);
+
+/* ----------------------------------------------------------------- errors
+ * Device error counter: malformed child entries met and traversal step caps
+ * hit, summed over all kernels since load or the last reset.  Reading
+ * synchronises the current device. */
+po_status po_device_errors(int64_t* count);
+po_status po_device_errors_reset(void);
+const char* po_status_str(po_status s);
+const char* po_last_error(void);
+/* Library version string, e.g. "plenoctree-mi355x 0.1 gfx950". */
+const char* po_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PLENOCTREE_H */

@@ -1,1 +1,12 @@
-"""MI355X-native PlenOctree renderer (placeholder; filled in below)."""
+"""MI355X-native PlenOctree renderer (arXiv 2103.14024).
+
+Hand-written HIP kernels for gfx950 behind a C ABI (include/plenoctree.h,
+libplenoctree.so); this package is the thin Python binding over it.  torch is
+used for device memory and streams only.
+
+    from paper_2103_14024_amd import Tree, Camera, render_camera
+"""
+from ._lib import PlenOctreeError, version  # noqa: F401
+from .render import (Camera, Job, device_errors, make_opts, render_batch, render_camera,  # noqa: F401
+                     render_rays, render_rays_backward, render_rays_differentiable, reset_device_errors)
+from .tree import Tree, build_host, default_stride, validate_host  # noqa: F401

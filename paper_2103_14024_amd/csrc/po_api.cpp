@@ -1,0 +1,495 @@
+// Host side of libplenoctree: the extern "C" entry points declared in
+// include/plenoctree.h.  Validates every argument before any GPU work,
+// builds octrees from leaf-cell lists (Sec. 4.2, "Filtering": surviving
+// voxels become leaves, everything else is empty), checks child arrays, and
+// forwards renders to the HIP launchers in po_kernels.hip.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "po_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+po_status fail(po_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+po_status ok() {
+    g_err.clear();
+    return PO_OK;
+}
+
+po_status device_fail(hipError_t e, const char* what) {
+    return fail(PO_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite(float v) { return std::isfinite(v); }
+
+int elem_size(int32_t dtype) { return dtype == PO_F16 ? 2 : 4; }
+
+po_status check_desc(const po_tree_desc* d) {
+    if (!d) return fail(PO_ERR_INVALID, "tree description is NULL");
+    if (d->depth < 1 || d->depth > PO_MAX_DEPTH)
+        return fail(PO_ERR_INVALID, "depth %d outside [1, %d]", d->depth, PO_MAX_DEPTH);
+    if (d->sh_degree < 0 || d->sh_degree > PO_MAX_SH_DEGREE)
+        return fail(PO_ERR_INVALID, "sh_degree %d outside [0, %d]", d->sh_degree, PO_MAX_SH_DEGREE);
+    if (!(d->half_size > 0.0f) || !finite(d->half_size))
+        return fail(PO_ERR_INVALID, "half_size must be finite and > 0");
+    for (int k = 0; k < 3; ++k)
+        if (!finite(d->center[k])) return fail(PO_ERR_INVALID, "center must be finite");
+    if (d->dtype != PO_F32 && d->dtype != PO_F16) return fail(PO_ERR_INVALID, "unknown dtype %d", d->dtype);
+    const int K = (d->sh_degree + 1) * (d->sh_degree + 1);
+    const int stride = d->sh_stride ? d->sh_stride : 3 * K;
+    if (stride < 3 * K) return fail(PO_ERR_INVALID, "sh_stride %d < 3*K = %d", stride, 3 * K);
+    if ((stride * elem_size(d->dtype)) % 4 != 0)
+        return fail(PO_ERR_INVALID, "sh_stride * element size (%d bytes) must be a multiple of 4",
+                    stride * elem_size(d->dtype));
+    return PO_OK;
+}
+
+po_status check_opts(const po_render_opts* o) {
+    if (!o) return fail(PO_ERR_INVALID, "render options are NULL");
+    for (int k = 0; k < 3; ++k)
+        if (!finite(o->bg[k])) return fail(PO_ERR_INVALID, "background must be finite");
+    if (!(o->stop_T >= 0.0f) || !finite(o->stop_T)) return fail(PO_ERR_INVALID, "stop_T must be finite and >= 0");
+    if (o->max_steps < 0) return fail(PO_ERR_INVALID, "max_steps must be >= 0");
+    if (o->flags & ~PO_OUT_AUX) return fail(PO_ERR_INVALID, "unknown flags 0x%x", o->flags);
+    return PO_OK;
+}
+
+KOpts kopts(const po_tree* t, const po_render_opts* o) {
+    KOpts k;
+    for (int i = 0; i < 3; ++i) k.bg[i] = o->bg[i];
+    k.stop_T = o->stop_T;
+    k.max_steps = o->max_steps ? o->max_steps : 3 * (1 << t->desc.depth) + 8;
+    k.flags = o->flags;
+    return k;
+}
+
+po_status check_camera(const po_camera* c) {
+    if (!c) return fail(PO_ERR_INVALID, "camera is NULL");
+    if (c->width < 1 || c->height < 1 || c->width > 16384 || c->height > 16384)
+        return fail(PO_ERR_INVALID, "image size %dx%d outside [1, 16384]", c->width, c->height);
+    if (!finite(c->fx) || !finite(c->fy) || c->fx == 0.0f || c->fy == 0.0f || !finite(c->cx) || !finite(c->cy))
+        return fail(PO_ERR_INVALID, "camera intrinsics must be finite with fx, fy != 0");
+    for (int i = 0; i < 12; ++i)
+        if (!finite(c->c2w[i])) return fail(PO_ERR_INVALID, "camera pose must be finite");
+    return PO_OK;
+}
+
+int32_t tiles_of(const po_camera* c) {
+    return ((c->width + PO_TILE - 1) / PO_TILE) * ((c->height + PO_TILE - 1) / PO_TILE);
+}
+
+KCam kcam(const po_camera* c) {
+    KCam k;
+    std::memcpy(k.c2w, c->c2w, sizeof k.c2w);
+    k.W = c->width;
+    k.H = c->height;
+    k.fx = c->fx;
+    k.fy = c->fy;
+    k.cx = c->cx;
+    k.cy = c->cy;
+    return k;
+}
+
+// Morton key of finest-level coordinates: bit b of x, y, z goes to bits
+// 3b+2, 3b+1, 3b, so the low three bits of a level-L prefix are the child
+// slot 4*xbit + 2*ybit + zbit.
+uint64_t morton(uint64_t x, uint64_t y, uint64_t z, int D) {
+    uint64_t k = 0;
+    for (int b = 0; b < D; ++b)
+        k |= (((x >> b) & 1ull) << (3 * b + 2)) | (((y >> b) & 1ull) << (3 * b + 1)) | (((z >> b) & 1ull) << (3 * b));
+    return k;
+}
+
+}  // namespace
+
+struct po_builder {
+    po_tree_desc desc;
+    int64_t n_cells = 0;
+    std::vector<int64_t> order;          // cells sorted by Morton key of their corner
+    std::vector<uint64_t> key;           // key of order[r]
+    std::vector<int32_t> level;          // level of order[r]
+    std::vector<std::vector<uint64_t>> prefixes;  // per level 0..D-1: sorted prefixes of internal nodes
+    std::vector<int64_t> offset;         // first node id of each level
+    int64_t n_nodes = 0;
+};
+
+extern "C" {
+
+const char* po_status_str(po_status s) {
+    switch (s) {
+        case PO_OK: return "ok";
+        case PO_ERR_INVALID: return "invalid argument";
+        case PO_ERR_TREE: return "malformed tree";
+        case PO_ERR_OOM: return "out of host memory";
+        case PO_ERR_DEVICE: return "HIP device error";
+        case PO_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* po_last_error(void) { return g_err.c_str(); }
+
+const char* po_version(void) { return "plenoctree-mi355x 0.1 gfx950"; }
+
+po_status po_builder_create(const po_tree_desc* desc, int64_t n_cells, const int32_t* h_cells, po_builder** out) {
+    if (po_status s = check_desc(desc)) return s;
+    if (!out) return fail(PO_ERR_INVALID, "out is NULL");
+    if (n_cells < 0 || n_cells >= (1ll << 31) - 1) return fail(PO_ERR_INVALID, "n_cells %lld out of range", (long long)n_cells);
+    if (n_cells > 0 && !h_cells) return fail(PO_ERR_INVALID, "cells is NULL");
+    const int D = desc->depth;
+    po_builder* b = new (std::nothrow) po_builder();
+    if (!b) return fail(PO_ERR_OOM, "builder allocation");
+    try {
+        b->desc = *desc;
+        b->n_cells = n_cells;
+        std::vector<uint64_t> keys((size_t)n_cells);
+        for (int64_t q = 0; q < n_cells; ++q) {
+            const int32_t lv = h_cells[4 * q], i = h_cells[4 * q + 1], j = h_cells[4 * q + 2], k = h_cells[4 * q + 3];
+            if (lv < 1 || lv > D) {
+                delete b;
+                return fail(PO_ERR_TREE, "cell %lld: level %d outside [1, %d]", (long long)q, lv, D);
+            }
+            const int64_t n = 1ll << lv;
+            if (i < 0 || j < 0 || k < 0 || i >= n || j >= n || k >= n) {
+                delete b;
+                return fail(PO_ERR_TREE, "cell %lld: coordinates (%d, %d, %d) outside level %d", (long long)q, i, j, k, lv);
+            }
+            const int s = D - lv;
+            keys[q] = morton((uint64_t)i << s, (uint64_t)j << s, (uint64_t)k << s, D);
+        }
+        b->order.resize((size_t)n_cells);
+        for (int64_t q = 0; q < n_cells; ++q) b->order[q] = q;
+        std::sort(b->order.begin(), b->order.end(), [&](int64_t a, int64_t c) {
+            if (keys[a] != keys[c]) return keys[a] < keys[c];
+            return a < c;
+        });
+        b->key.resize((size_t)n_cells);
+        b->level.resize((size_t)n_cells);
+        for (int64_t r = 0; r < n_cells; ++r) {
+            b->key[r] = keys[b->order[r]];
+            b->level[r] = h_cells[4 * b->order[r]];
+        }
+        // A cell is the Morton interval [key, key + 8^(D - level)); cells overlap iff intervals do.
+        for (int64_t r = 1; r < n_cells; ++r) {
+            const uint64_t end_prev = b->key[r - 1] + (1ull << (3 * (D - b->level[r - 1])));
+            if (b->key[r] < end_prev) {
+                const long long a = (long long)b->order[r - 1], c = (long long)b->order[r];
+                delete b;
+                return fail(PO_ERR_TREE, "cells %lld and %lld overlap", a, c);
+            }
+        }
+        b->prefixes.assign(D, {});
+        b->prefixes[0].push_back(0);  // the root always exists
+        for (int L = 1; L < D; ++L) {
+            auto& P = b->prefixes[L];
+            for (int64_t r = 0; r < n_cells; ++r) {
+                if (b->level[r] <= L) continue;
+                const uint64_t p = b->key[r] >> (3 * (D - L));
+                if (P.empty() || P.back() != p) P.push_back(p);
+            }
+        }
+        b->offset.assign(D, 0);
+        int64_t total = 0;
+        for (int L = 0; L < D; ++L) {
+            b->offset[L] = total;
+            total += (int64_t)b->prefixes[L].size();
+        }
+        if (total >= (1ll << 31) / 8) {
+            delete b;
+            return fail(PO_ERR_INVALID, "tree needs %lld nodes, too many for int32 child entries", (long long)total);
+        }
+        b->n_nodes = total;
+    } catch (const std::bad_alloc&) {
+        delete b;
+        return fail(PO_ERR_OOM, "builder allocation");
+    }
+    *out = b;
+    return ok();
+}
+
+po_status po_builder_sizes(const po_builder* b, int64_t* n_nodes, int64_t* n_leaves) {
+    if (!b || !n_nodes || !n_leaves) return fail(PO_ERR_INVALID, "NULL argument");
+    *n_nodes = b->n_nodes;
+    *n_leaves = b->n_cells;
+    return ok();
+}
+
+po_status po_builder_emit(const po_builder* b, int32_t* h_child, int64_t* h_leaf_perm) {
+    if (!b || !h_child || (b->n_cells > 0 && !h_leaf_perm)) return fail(PO_ERR_INVALID, "NULL argument");
+    const int D = b->desc.depth;
+    std::memset(h_child, 0, sizeof(int32_t) * 8 * (size_t)b->n_nodes);
+    auto node_id = [&](int L, uint64_t p) -> int64_t {
+        const auto& P = b->prefixes[L];
+        const auto it = std::lower_bound(P.begin(), P.end(), p);
+        return b->offset[L] + (it - P.begin());
+    };
+    for (int L = 1; L < D; ++L) {
+        const auto& P = b->prefixes[L];
+        for (size_t q = 0; q < P.size(); ++q) {
+            const int64_t parent = node_id(L - 1, P[q] >> 3);
+            h_child[parent * 8 + (P[q] & 7)] = (int32_t)(b->offset[L] + (int64_t)q);
+        }
+    }
+    for (int64_t r = 0; r < b->n_cells; ++r) {
+        const int lv = b->level[r];
+        const uint64_t p = b->key[r] >> (3 * (D - lv));
+        const int64_t parent = node_id(lv - 1, p >> 3);
+        h_child[parent * 8 + (p & 7)] = (int32_t)(-r - 1);
+        h_leaf_perm[r] = b->order[r];
+    }
+    return ok();
+}
+
+po_status po_builder_destroy(po_builder* b) {
+    delete b;
+    return ok();
+}
+
+po_status po_tree_validate(const po_tree_desc* desc, int64_t n_nodes, const int32_t* h_child, int64_t n_leaves,
+                           const void* h_sigma) {
+    if (po_status s = check_desc(desc)) return s;
+    if (n_nodes < 1 || n_nodes >= (1ll << 31) / 8) return fail(PO_ERR_INVALID, "n_nodes %lld out of range", (long long)n_nodes);
+    if (n_leaves < 0 || n_leaves >= (1ll << 31) - 1) return fail(PO_ERR_INVALID, "n_leaves %lld out of range", (long long)n_leaves);
+    if (!h_child) return fail(PO_ERR_INVALID, "child array is NULL");
+    const int D = desc->depth;
+    try {
+        std::vector<int32_t> lvl((size_t)n_nodes, -1);
+        std::vector<uint8_t> leaf_seen((size_t)n_leaves, 0);
+        std::vector<int64_t> queue;
+        queue.reserve((size_t)n_nodes);
+        lvl[0] = 0;
+        queue.push_back(0);
+        for (size_t h = 0; h < queue.size(); ++h) {
+            const int64_t v = queue[h];
+            for (int c = 0; c < 8; ++c) {
+                const int32_t e = h_child[v * 8 + c];
+                if (e > 0) {
+                    if (e >= n_nodes)
+                        return fail(PO_ERR_TREE, "node %lld slot %d: child %d outside [1, %lld)", (long long)v, c, e, (long long)n_nodes);
+                    if (lvl[e] >= 0)
+                        return fail(PO_ERR_TREE, "node %d is referenced more than once (cycle or shared subtree)", e);
+                    if (lvl[v] + 1 >= D)
+                        return fail(PO_ERR_TREE, "node %d is an internal node at depth %d (max depth %d)", e, lvl[v] + 1, D);
+                    lvl[e] = lvl[v] + 1;
+                    queue.push_back(e);
+                } else if (e < 0) {
+                    const int64_t leaf = -(int64_t)e - 1;
+                    if (leaf >= n_leaves)
+                        return fail(PO_ERR_TREE, "node %lld slot %d: leaf %lld outside [0, %lld)", (long long)v, c, (long long)leaf, (long long)n_leaves);
+                    if (leaf_seen[leaf]) return fail(PO_ERR_TREE, "leaf %lld is referenced more than once", (long long)leaf);
+                    leaf_seen[leaf] = 1;
+                }
+            }
+        }
+        if ((int64_t)queue.size() != n_nodes)
+            return fail(PO_ERR_TREE, "%lld of %lld nodes are unreachable from the root", (long long)(n_nodes - (int64_t)queue.size()), (long long)n_nodes);
+    } catch (const std::bad_alloc&) {
+        return fail(PO_ERR_OOM, "validator allocation");
+    }
+    if (h_sigma) {
+        for (int64_t i = 0; i < n_leaves; ++i) {
+            bool bad;
+            if (desc->dtype == PO_F32) {
+                bad = !std::isfinite(static_cast<const float*>(h_sigma)[i]);
+            } else {
+                const uint16_t h = static_cast<const uint16_t*>(h_sigma)[i];
+                bad = ((h >> 10) & 0x1f) == 0x1f;
+            }
+            if (bad) return fail(PO_ERR_TREE, "leaf %lld has a non-finite density", (long long)i);
+        }
+    }
+    return ok();
+}
+
+po_status po_tree_bind(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
+                       const void* d_sigma, const void* d_sh, po_tree** out) {
+    if (po_status s = check_desc(desc)) return s;
+    if (!out) return fail(PO_ERR_INVALID, "out is NULL");
+    if (n_nodes < 1 || n_nodes >= (1ll << 31) / 8) return fail(PO_ERR_INVALID, "n_nodes %lld out of range", (long long)n_nodes);
+    if (n_leaves < 0 || n_leaves >= (1ll << 31) - 1) return fail(PO_ERR_INVALID, "n_leaves %lld out of range", (long long)n_leaves);
+    if (!d_child) return fail(PO_ERR_INVALID, "child array is NULL");
+    if (n_leaves > 0 && (!d_sigma || !d_sh)) return fail(PO_ERR_INVALID, "leaf arrays are NULL");
+    const int es = elem_size(desc->dtype);
+    if (((uintptr_t)d_child) % 4 || ((uintptr_t)d_sigma) % es || ((uintptr_t)d_sh) % 4)
+        return fail(PO_ERR_INVALID, "misaligned device array");
+    po_tree* t = new (std::nothrow) po_tree();
+    if (!t) return fail(PO_ERR_OOM, "tree handle allocation");
+    t->desc = *desc;
+    t->n_nodes = n_nodes;
+    t->n_leaves = n_leaves;
+    t->child = d_child;
+    t->sigma = d_sigma;
+    t->sh = d_sh;
+    t->K = (desc->sh_degree + 1) * (desc->sh_degree + 1);
+    t->stride = desc->sh_stride ? desc->sh_stride : 3 * t->K;
+    const size_t rb = (size_t)t->stride * es;
+    t->vec_bytes = 4;
+    for (int v : {16, 8}) {
+        if (((uintptr_t)d_sh) % v == 0 && rb % v == 0) {
+            t->vec_bytes = v;
+            break;
+        }
+    }
+    KTree& k = t->kt;
+    k.child = d_child;
+    k.sigma = d_sigma;
+    k.sh = d_sh;
+    k.n_nodes = (int32_t)n_nodes;
+    k.n_leaves = (int32_t)n_leaves;
+    k.stride = t->stride;
+    k.depth = desc->depth;
+    for (int a = 0; a < 3; ++a) k.lo[a] = (double)desc->center[a] - (double)desc->half_size;
+    k.scale = (double)(1 << desc->depth) / (2.0 * (double)desc->half_size);
+    *out = t;
+    return ok();
+}
+
+po_status po_tree_destroy(po_tree* t) {
+    delete t;
+    return ok();
+}
+
+po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, const float* d_dirs,
+                         const po_render_opts* opts, float* d_rgb, float* d_aux, void* stream) {
+    if (!t) return fail(PO_ERR_INVALID, "tree is NULL");
+    if (po_status s = check_opts(opts)) return s;
+    if (n < 0) return fail(PO_ERR_INVALID, "n = %lld < 0", (long long)n);
+    if (n == 0) return ok();
+    if (n > (1ll << 40)) return fail(PO_ERR_INVALID, "n = %lld too large", (long long)n);
+    if (!d_origins || !d_dirs || !d_rgb) return fail(PO_ERR_INVALID, "ray or output array is NULL");
+    if ((opts->flags & PO_OUT_AUX) && !d_aux) return fail(PO_ERR_INVALID, "PO_OUT_AUX set but aux is NULL");
+    float* aux = (opts->flags & PO_OUT_AUX) ? d_aux : nullptr;
+    hipError_t e = po_launch_rays(t, n, d_origins, d_dirs, kopts(t, opts), d_rgb, aux, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "render_rays launch");
+    return ok();
+}
+
+po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_render_opts* opts, float* d_rgb,
+                           float* d_aux, void* stream) {
+    if (!t) return fail(PO_ERR_INVALID, "tree is NULL");
+    if (po_status s = check_camera(cam)) return s;
+    if (po_status s = check_opts(opts)) return s;
+    if (!d_rgb) return fail(PO_ERR_INVALID, "output image is NULL");
+    if ((opts->flags & PO_OUT_AUX) && !d_aux) return fail(PO_ERR_INVALID, "PO_OUT_AUX set but aux is NULL");
+    KJob j;
+    std::memset(&j, 0, sizeof j);
+    j.tr = t->kt;
+    j.cam = kcam(cam);
+    j.op = kopts(t, opts);
+    j.rgb = d_rgb;
+    j.aux = (opts->flags & PO_OUT_AUX) ? d_aux : nullptr;
+    j.tile_begin = 0;
+    j.block_begin = 0;
+    j.tiles_x = (cam->width + PO_TILE - 1) / PO_TILE;
+    hipError_t e = po_launch_camera_jobs(t, 1, &j, tiles_of(cam), (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "render_camera launch");
+    return ok();
+}
+
+po_status po_render_rays_backward(const po_tree* t, int64_t n, const float* d_origins, const float* d_dirs,
+                                  const po_render_opts* opts, const float* d_rgb_fwd, const float* d_grad_rgb,
+                                  float* d_grad_sigma, float* d_grad_sh, void* stream) {
+    if (!t) return fail(PO_ERR_INVALID, "tree is NULL");
+    if (po_status s = check_opts(opts)) return s;
+    if (t->desc.dtype != PO_F32) return fail(PO_ERR_UNSUPPORTED, "gradients need float32 leaves");
+    if (n < 0) return fail(PO_ERR_INVALID, "n = %lld < 0", (long long)n);
+    if (n == 0) return ok();
+    if (n > (1ll << 40)) return fail(PO_ERR_INVALID, "n = %lld too large", (long long)n);
+    if (!d_origins || !d_dirs || !d_rgb_fwd || !d_grad_rgb || !d_grad_sigma || !d_grad_sh)
+        return fail(PO_ERR_INVALID, "NULL array");
+    hipError_t e = po_launch_backward(t, n, d_origins, d_dirs, kopts(t, opts), d_rgb_fwd, d_grad_rgb, d_grad_sigma,
+                                      d_grad_sh, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "backward launch");
+    return ok();
+}
+
+po_status po_camera_tiles(const po_camera* cam, int32_t* n_tiles) {
+    if (po_status s = check_camera(cam)) return s;
+    if (!n_tiles) return fail(PO_ERR_INVALID, "n_tiles is NULL");
+    *n_tiles = tiles_of(cam);
+    return ok();
+}
+
+po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream) {
+    if (n_jobs < 0 || n_jobs > PO_BATCH_MAX_JOBS)
+        return fail(PO_ERR_INVALID, "n_jobs %d outside [0, %d]", n_jobs, PO_BATCH_MAX_JOBS);
+    if (n_jobs == 0) return ok();
+    if (!jobs) return fail(PO_ERR_INVALID, "jobs is NULL");
+    for (int i = 0; i < n_jobs; ++i) {
+        const po_job& J = jobs[i];
+        if (!J.tree) return fail(PO_ERR_INVALID, "job %d: tree is NULL", i);
+        if (po_status s = check_camera(&J.cam)) return fail(s, "job %d: %s", i, g_err.c_str());
+        if (po_status s = check_opts(&J.opts)) return fail(s, "job %d: %s", i, g_err.c_str());
+        if (!J.d_rgb) return fail(PO_ERR_INVALID, "job %d: output image is NULL", i);
+        if ((J.opts.flags & PO_OUT_AUX) && !J.d_aux) return fail(PO_ERR_INVALID, "job %d: PO_OUT_AUX set but aux is NULL", i);
+        if (J.tile_begin < 0 || J.tile_end < J.tile_begin || J.tile_end > tiles_of(&J.cam))
+            return fail(PO_ERR_INVALID, "job %d: tile range [%d, %d) outside [0, %d]", i, J.tile_begin, J.tile_end,
+                        tiles_of(&J.cam));
+    }
+    // group jobs by kernel variant, one launch per group, in order of first appearance
+    bool done[PO_BATCH_MAX_JOBS] = {false};
+    for (int i = 0; i < n_jobs; ++i) {
+        if (done[i]) continue;
+        const int plan = po_plan_id(jobs[i].tree);
+        KJob kj[PO_BATCH_MAX_JOBS];
+        int nj = 0, blocks = 0;
+        for (int q = i; q < n_jobs; ++q) {
+            if (done[q] || po_plan_id(jobs[q].tree) != plan) continue;
+            done[q] = true;
+            const po_job& J = jobs[q];
+            const int nt = J.tile_end - J.tile_begin;
+            if (nt == 0) continue;
+            KJob& k = kj[nj++];
+            std::memset(&k, 0, sizeof k);
+            k.tr = J.tree->kt;
+            k.cam = kcam(&J.cam);
+            k.op = kopts(J.tree, &J.opts);
+            k.rgb = J.d_rgb;
+            k.aux = (J.opts.flags & PO_OUT_AUX) ? J.d_aux : nullptr;
+            k.tile_begin = J.tile_begin;
+            k.block_begin = blocks;
+            k.tiles_x = (J.cam.width + PO_TILE - 1) / PO_TILE;
+            blocks += nt;
+        }
+        if (nj == 0) continue;
+        hipError_t e = po_launch_camera_jobs(jobs[i].tree, nj, kj, blocks, (hipStream_t)stream);
+        if (e != hipSuccess) return device_fail(e, "render_batch launch");
+    }
+    return ok();
+}
+
+po_status po_device_errors(int64_t* count) {
+    if (!count) return fail(PO_ERR_INVALID, "count is NULL");
+    unsigned long long v = 0;
+    hipError_t e = po_read_device_errors(&v);
+    if (e != hipSuccess) return device_fail(e, "reading the device error counter");
+    *count = (int64_t)v;
+    return ok();
+}
+
+po_status po_device_errors_reset(void) {
+    hipError_t e = po_reset_device_errors();
+    if (e != hipSuccess) return device_fail(e, "resetting the device error counter");
+    return ok();
+}
+
+}  // extern "C"

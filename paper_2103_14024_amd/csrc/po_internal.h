@@ -1,0 +1,74 @@
+// Internal declarations shared by the host API (po_api.cpp) and the HIP
+// kernels (po_kernels.hip) of libplenoctree.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "plenoctree.h"
+
+// Kernel-side view of a bound tree (plain data, passed by value).
+struct KTree {
+    const int32_t* child;   // [n_nodes][8]
+    const void* sigma;      // [n_leaves] float or half
+    const void* sh;         // [n_leaves][stride] float or half
+    int32_t n_nodes;
+    int32_t n_leaves;
+    int32_t stride;         // elements per SH record
+    int32_t depth;          // D
+    double lo[3];           // box minimum corner, world units
+    double scale;           // grid units (finest cells) per world unit: 2^D / (2 half)
+};
+
+struct KOpts {
+    float bg[3];
+    float stop_T;
+    int32_t max_steps;
+    uint32_t flags;
+};
+
+struct KCam {
+    float c2w[12];
+    int32_t W, H;
+    float fx, fy, cx, cy;
+};
+
+// One camera job of a batched launch.
+struct KJob {
+    KTree tr;
+    KCam cam;
+    KOpts op;
+    float* rgb;
+    float* aux;
+    int32_t tile_begin;     // first 16x16 tile of the image rendered by this job
+    int32_t block_begin;    // first workgroup (before the XCD swizzle) of this job
+    int32_t tiles_x;        // ceil(W / 16)
+    int32_t pad_;
+};
+
+struct po_tree {
+    po_tree_desc desc;
+    int64_t n_nodes, n_leaves;
+    const int32_t* child;
+    const void* sigma;
+    const void* sh;
+    int32_t K;              // coefficients per channel
+    int32_t stride;         // elements per SH record
+    int32_t vec_bytes;      // widest aligned load of a record: 16, 8 or 4
+    KTree kt;
+};
+
+// Launchers (po_kernels.hip).  Arguments are validated by the caller.
+hipError_t po_launch_rays(const po_tree* t, int64_t n, const float* o, const float* d,
+                          const KOpts& op, float* rgb, float* aux, hipStream_t s);
+hipError_t po_launch_backward(const po_tree* t, int64_t n, const float* o, const float* d,
+                              const KOpts& op, const float* rgb_fwd, const float* grad_rgb,
+                              float* grad_sigma, float* grad_sh, hipStream_t s);
+// Renders camera jobs that all share dtype, K and vec_bytes (at most PO_BATCH_MAX_JOBS).
+hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks,
+                                 hipStream_t s);
+hipError_t po_read_device_errors(unsigned long long* out);
+// Kernel variant a tree renders with (dtype, K, record-load plan); jobs of one
+// batched launch must share it.
+int po_plan_id(const po_tree* t);
+hipError_t po_reset_device_errors();

@@ -1,0 +1,585 @@
+// HIP kernels of libplenoctree for gfx950 (MI355X).
+//
+// One ray per lane.  A ray is cut into the exact segments between voxel
+// boundaries of the sparse octree (Sec. 4.2, "Rendering"): the current
+// position is kept as integer coordinates of a finest-level cell; each step
+// descends from the root to the leaf containing it, computes the parameter at
+// which the ray leaves that leaf's cube (the nearest exit plane), composites
+// the segment if the leaf holds data, and moves the coordinates across the
+// exit face.  Large empty cubes are therefore crossed in one step.  Each data
+// segment is shaded with the sigmoid of the real-SH expansion in the ray
+// direction (Sec. 4.1; SH of App. B.1) and composited front to back with
+// alpha = 1 - exp(-sigma delta) (Sec. 3, eqn:quad); marching stops once the
+// transmittance falls below the threshold (Sec. 4.2) and the background
+// takes the remaining transmittance (App. B.3).
+//
+// The backward kernel replays the identical segment sequence and applies the
+// analytic derivatives of App. B.3 with the prefix scheme of its Remark.
+//
+// Ray geometry (crossing parameters, positions) is evaluated in FP64, leaf
+// values, SH and compositing in FP32.  The library is compiled with
+// -ffp-contract=off: every fused multiply-add is written out, so the forward
+// and backward kernels take bit-identical steps.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "po_internal.h"
+
+__device__ unsigned long long g_po_errors = 0;
+
+namespace {
+
+constexpr int kBlock = 256;  // 4 wave64 per workgroup
+
+// ---------------------------------------------------------------------------
+// Real SH basis up to degree 3 at a unit direction (App. B.1), written as
+// polynomials in x, y, z.  Index l*l + l + m.  Sign convention: P_l^m carries
+// the Condon-Shortley phase, which cancels the (-1)^m of the real
+// combination, so every coefficient below is positive.
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float (&Y)[K]) {
+    Y[0] = 0.28209479177387814f;  // 1/(2 sqrt(pi))
+    if constexpr (K > 1) {
+        Y[1] = 0.4886025119029199f * y;  // sqrt(3/(4 pi))
+        Y[2] = 0.4886025119029199f * z;
+        Y[3] = 0.4886025119029199f * x;
+    }
+    if constexpr (K > 4) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = 1.0925484305920792f * (x * y);              // sqrt(15/pi)/2
+        Y[5] = 1.0925484305920792f * (y * z);
+        Y[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);  // sqrt(5/pi)/4
+        Y[7] = 1.0925484305920792f * (x * z);
+        Y[8] = 0.5462742152960396f * (xx - yy);            // sqrt(15/pi)/4
+        if constexpr (K > 9) {
+            Y[9] = 0.5900435899266435f * (y * (3.0f * xx - yy));   // sqrt(35/(2 pi))/4
+            Y[10] = 2.890611442640554f * (x * y * z);              // sqrt(105/pi)/2
+            Y[11] = 0.4570457994644658f * (y * (5.0f * zz - 1.0f)); // sqrt(21/(2 pi))/4
+            Y[12] = 0.3731763325901154f * (z * (5.0f * zz - 3.0f)); // sqrt(7/pi)/4
+            Y[13] = 0.4570457994644658f * (x * (5.0f * zz - 1.0f));
+            Y[14] = 1.445305721320277f * (z * (xx - yy));           // sqrt(105/pi)/4
+            Y[15] = 0.5900435899266435f * (x * (xx - 3.0f * yy));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Leaf record access.  T is float or __half; values are widened to float.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float load_sigma(const float* p, int i) { return p[i]; }
+__device__ __forceinline__ float load_sigma(const __half* p, int i) { return __half2float(p[i]); }
+
+// Loads NL elements of one SH record at `base` using VEC-byte loads (16, 8 or
+// 4; `base` is VEC-aligned) followed by dword loads and, for an odd number
+// of halves, one 2-byte load.  The host guarantees NL elements lie inside
+// the record (NL <= stride).
+template <typename T, int NL, int VEC>
+__device__ __forceinline__ void load_record(const char* __restrict__ base, float (&out)[NL]) {
+    constexpr int NB = NL * (int)sizeof(T);
+    constexpr int NW = (NB + 3) / 4;
+    constexpr int NV = NB / VEC;
+    constexpr int DONE = NV * VEC / 4;
+    constexpr int FULLW = NB / 4;
+    uint32_t w[NW];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if constexpr (VEC == 16) {
+            const uint4 q = *reinterpret_cast<const uint4*>(base + 16 * v);
+            w[4 * v + 0] = q.x;
+            w[4 * v + 1] = q.y;
+            w[4 * v + 2] = q.z;
+            w[4 * v + 3] = q.w;
+        } else if constexpr (VEC == 8) {
+            const uint2 q = *reinterpret_cast<const uint2*>(base + 8 * v);
+            w[2 * v + 0] = q.x;
+            w[2 * v + 1] = q.y;
+        } else {
+            w[v] = *reinterpret_cast<const uint32_t*>(base + 4 * v);
+        }
+    }
+#pragma unroll
+    for (int i = DONE; i < FULLW; ++i) w[i] = *reinterpret_cast<const uint32_t*>(base + 4 * i);
+    if constexpr (NB % 4 != 0) w[FULLW] = *reinterpret_cast<const uint16_t*>(base + 4 * FULLW);
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        if constexpr (sizeof(T) == 4) {
+            out[i] = __uint_as_float(w[i]);
+        } else {
+            const uint32_t h = (i & 1) ? (w[i >> 1] >> 16) : (w[i >> 1] & 0xffffu);
+            out[i] = __half2float(__ushort_as_half((unsigned short)h));
+        }
+    }
+}
+
+__device__ __forceinline__ float sigmoid(float z) { return __frcp_rn(1.0f + __expf(-z)); }
+
+// ---------------------------------------------------------------------------
+// Ray geometry in grid units: the box spans [0, 2^D]^3 and finest cells have
+// unit edge.  The ray is og + s * dg with dg the caller's (unnormalised)
+// direction scaled to grid units, so no rounding enters the direction; the
+// origin transform, the plane-crossing parameters s and the positions are
+// evaluated in FP64.  In FP32 the crossing parameter of a far plane carries
+// an error of about 2^-24 of the distance travelled, which becomes an error of
+// every segment length; with densities of several hundred per unit length
+// that exceeds 1e-4 in colour.  Leaf values, SH and compositing stay FP32.
+// A segment's length in world units is (s_exit - s_entry) * |d|.
+// ---------------------------------------------------------------------------
+struct Ray {
+    double og[3];  // origin, grid units
+    double dg[3];  // direction (caller's length), grid units per unit of s
+    double inv[3]; // 1 / dg (0 where dg == 0; never used there)
+    double len;    // |d| in world units
+    float dn[3];   // unit direction, world (SH argument)
+    int c[3];      // finest-level coordinates of the current cell
+    double s;      // current parameter
+};
+
+__device__ __forceinline__ bool ray_setup(const KTree& tr, float ox, float oy, float oz, float dx,
+                                          float dy, float dz, Ray& r) {
+    const double d[3] = {(double)dx, (double)dy, (double)dz};
+    const double o[3] = {(double)ox, (double)oy, (double)oz};
+    const double len2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (!(len2 > 0.0) || !(len2 < 1e300)) return false;
+    r.len = sqrt(len2);
+    const double il = 1.0 / r.len;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r.dn[k] = (float)(d[k] * il);
+    const double N = (double)(1 << tr.depth);
+    double s0 = 0.0, s1 = 1e300;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r.og[k] = (o[k] - tr.lo[k]) * tr.scale;
+        if (!(fabs(r.og[k]) < 1e300)) return false;
+        r.dg[k] = d[k] * tr.scale;
+        if (r.dg[k] == 0.0) {
+            r.inv[k] = 0.0;
+            if (!(r.og[k] >= 0.0 && r.og[k] < N)) return false;  // half-open cell in a grid plane
+        } else {
+            r.inv[k] = 1.0 / r.dg[k];
+            const double ta = (0.0 - r.og[k]) * r.inv[k];
+            const double tb = (N - r.og[k]) * r.inv[k];
+            s0 = fmax(s0, fmin(ta, tb));
+            s1 = fmin(s1, fmax(ta, tb));
+        }
+    }
+    if (!(s1 > s0)) return false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double p = (r.dg[k] == 0.0) ? r.og[k] : fma(s0, r.dg[k], r.og[k]);
+        r.c[k] = (int)fmin(fmax(floor(p), 0.0), N - 1.0);
+    }
+    r.s = s0;
+    return true;
+}
+
+// Walks the segments of a ray.  For every data leaf crossed over a positive
+// length, calls on_sample(leaf, delta) with delta in world units; a true
+// return stops the walk.  Returns the number of cells visited.
+template <class OnSample>
+__device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, OnSample&& on_sample) {
+    const int D = tr.depth;
+    const int N = 1 << D;
+    int steps = 0;
+    while (true) {
+        // descend from the root to the leaf (data or empty) holding cell c
+        int node = 0, L = 0, e;
+        while (true) {
+            const int sft = D - 1 - L;
+            const int oct = (((r.c[0] >> sft) & 1) << 2) | (((r.c[1] >> sft) & 1) << 1) | ((r.c[2] >> sft) & 1);
+            e = __ldg(tr.child + ((size_t)node * 8 + oct));
+            ++L;
+            if (e <= 0) break;
+            if (L >= D || e >= tr.n_nodes) {  // malformed: treat as empty
+                atomicAdd(&g_po_errors, 1ull);
+                e = 0;
+                break;
+            }
+            node = e;
+        }
+        int leaf = -1;
+        if (e < 0) {
+            leaf = -1 - e;
+            if (leaf >= tr.n_leaves) {
+                atomicAdd(&g_po_errors, 1ull);
+                leaf = -1;
+            }
+        }
+        const int csz = 1 << (D - L);
+        int lo[3];
+        double sk[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = r.c[k] & ~(csz - 1);
+            if (r.dg[k] > 0.0)
+                sk[k] = ((double)(lo[k] + csz) - r.og[k]) * r.inv[k];
+            else if (r.dg[k] < 0.0)
+                sk[k] = ((double)lo[k] - r.og[k]) * r.inv[k];
+            else
+                sk[k] = 1e300;
+        }
+        const double se = fmax(fmin(fmin(sk[0], sk[1]), sk[2]), r.s);
+        ++steps;
+        if (leaf >= 0) {
+            const float delta = (float)((se - r.s) * r.len);
+            if (delta > 0.0f && on_sample(leaf, delta)) break;
+        }
+        // move across the exit face(s)
+        bool out = false;
+        int nc[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (sk[k] <= se) {
+                nc[k] = (r.dg[k] > 0.0) ? lo[k] + csz : lo[k] - 1;
+                out |= (nc[k] < 0) | (nc[k] >= N);
+            } else if (r.dg[k] != 0.0) {
+                double p = fma(se, r.dg[k], r.og[k]);
+                p = fmin(fmax(p, (double)lo[k]), (double)(lo[k] + csz - 1));
+                const int q = (int)floor(p);
+                nc[k] = (r.dg[k] > 0.0) ? max(q, r.c[k]) : min(q, r.c[k]);
+            } else {
+                nc[k] = r.c[k];
+            }
+        }
+        r.s = se;
+        if (out) break;
+        r.c[0] = nc[0];
+        r.c[1] = nc[1];
+        r.c[2] = nc[2];
+        if (steps >= max_steps) {
+            atomicAdd(&g_po_errors, 1ull);
+            break;
+        }
+    }
+    return steps;
+}
+
+template <int K>
+__device__ __forceinline__ float dot_channel(const float* rec, const float (&Y)[K]) {
+    float z = rec[0] * Y[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) z = fmaf(rec[k], Y[k], z);
+    return z;
+}
+
+// Renders one ray: colour (background included), final T, samples, steps.
+template <typename T, int K, int VEC, int NL>
+__device__ __forceinline__ void render_one(const KTree& tr, const KOpts& op, float ox, float oy, float oz,
+                                           float dx, float dy, float dz, float (&C)[3], float& Tr,
+                                           int& ns, int& steps) {
+    C[0] = C[1] = C[2] = 0.0f;
+    Tr = 1.0f;
+    ns = 0;
+    steps = 0;
+    Ray r;
+    if (ray_setup(tr, ox, oy, oz, dx, dy, dz, r)) {
+        float Y[K];
+        sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], Y);
+        const T* sig = static_cast<const T*>(tr.sigma);
+        const char* shb = static_cast<const char*>(tr.sh);
+        const size_t rec_bytes = (size_t)tr.stride * sizeof(T);
+        const float stopT = op.stop_T;
+        float Tl = 1.0f;
+        int nsl = 0;
+        float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+        steps = march(tr, r, op.max_steps, [&](int leaf, float delta) -> bool {
+            ++nsl;
+            const float s = fmaxf(load_sigma(sig, leaf), 0.0f);
+            if (!(s > 0.0f)) return false;
+            float rec[NL];
+            load_record<T, NL, VEC>(shb + (size_t)leaf * rec_bytes, rec);
+            const float ex = __expf(-(s * delta));
+            const float w = Tl * (1.0f - ex);
+            c0 = fmaf(w, sigmoid(dot_channel<K>(rec, Y)), c0);
+            c1 = fmaf(w, sigmoid(dot_channel<K>(rec + K, Y)), c1);
+            c2 = fmaf(w, sigmoid(dot_channel<K>(rec + 2 * K, Y)), c2);
+            Tl = Tl * ex;
+            return Tl < stopT;
+        });
+        C[0] = c0;
+        C[1] = c1;
+        C[2] = c2;
+        Tr = Tl;
+        ns = nsl;
+    }
+    C[0] = fmaf(Tr, op.bg[0], C[0]);
+    C[1] = fmaf(Tr, op.bg[1], C[1]);
+    C[2] = fmaf(Tr, op.bg[2], C[2]);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b % 8).  Remap so that each XCD receives one contiguous range of the
+// logical workgroup order (neighbouring tiles share its L2).  The grid has
+// 8 * ceil(n / 8) workgroups; returns -1 for the padding ones.
+__device__ __forceinline__ int64_t xcd_swizzle(int64_t b, int64_t n_logical) {
+    const int64_t per = (n_logical + 7) / 8;
+    const int64_t l = (b % 8) * per + b / 8;
+    return l < n_logical ? l : -1;
+}
+
+template <typename T, int K, int VEC, int NL>
+__global__ __launch_bounds__(kBlock) void k_render_rays(KTree tr, int64_t n, int64_t n_blocks,
+                                                        const float* __restrict__ o,
+                                                        const float* __restrict__ d, KOpts op,
+                                                        float* __restrict__ rgb, float* __restrict__ aux) {
+    const int64_t blk = xcd_swizzle(blockIdx.x, n_blocks);
+    if (blk < 0) return;
+    const int64_t i = blk * kBlock + threadIdx.x;
+    if (i >= n) return;
+    float C[3], Tr;
+    int ns, steps;
+    render_one<T, K, VEC, NL>(tr, op, o[3 * i], o[3 * i + 1], o[3 * i + 2], d[3 * i], d[3 * i + 1],
+                              d[3 * i + 2], C, Tr, ns, steps);
+    rgb[3 * i + 0] = C[0];
+    rgb[3 * i + 1] = C[1];
+    rgb[3 * i + 2] = C[2];
+    if (aux) {
+        aux[3 * i + 0] = Tr;
+        aux[3 * i + 1] = (float)ns;
+        aux[3 * i + 2] = (float)steps;
+    }
+}
+
+template <int MAXJ>
+struct KBatch {
+    KJob job[MAXJ];
+    int32_t n_jobs;
+    int32_t n_blocks;
+};
+
+// Camera jobs: one workgroup renders one 16x16 tile; wave w takes the 8x8
+// quadrant (w & 1, w >> 1) and lane l the pixel (l & 7, l >> 3) of it.
+template <typename T, int K, int VEC, int NL, int MAXJ>
+__global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
+    const int64_t b = xcd_swizzle(blockIdx.x, B.n_blocks);
+    if (b < 0) return;
+    int j = 0;
+    if constexpr (MAXJ > 1) {
+        for (int q = 1; q < B.n_jobs; ++q)
+            if (b >= B.job[q].block_begin) j = q;
+    }
+    const KJob& J = B.job[j];
+    const int tile = J.tile_begin + (int)(b - J.block_begin);
+    const int tx = tile % J.tiles_x, ty = tile / J.tiles_x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int px = tx * 16 + (wave & 1) * 8 + (lane & 7);
+    const int py = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+    if (px >= J.cam.W || py >= J.cam.H) return;
+    const float x = ((float)px + 0.5f - J.cam.cx) / J.cam.fx;
+    const float y = -(((float)py + 0.5f - J.cam.cy) / J.cam.fy);
+    const float* M = J.cam.c2w;
+    const float dx = M[0] * x + M[1] * y - M[2];
+    const float dy = M[4] * x + M[5] * y - M[6];
+    const float dz = M[8] * x + M[9] * y - M[10];
+    float C[3], Tr;
+    int ns, steps;
+    render_one<T, K, VEC, NL>(J.tr, J.op, M[3], M[7], M[11], dx, dy, dz, C, Tr, ns, steps);
+    const size_t p = (size_t)py * J.cam.W + px;
+    J.rgb[3 * p + 0] = C[0];
+    J.rgb[3 * p + 1] = C[1];
+    J.rgb[3 * p + 2] = C[2];
+    if (J.aux) {
+        J.aux[3 * p + 0] = Tr;
+        J.aux[3 * p + 1] = (float)ns;
+        J.aux[3 * p + 2] = (float)steps;
+    }
+}
+
+// Backward (App. B.3): replays the forward walk; C is the forward colour.
+template <int K, int VEC, int NL>
+__global__ __launch_bounds__(kBlock) void k_backward(KTree tr, int64_t n, int64_t n_blocks,
+                                                     const float* __restrict__ o,
+                                                     const float* __restrict__ d, KOpts op,
+                                                     const float* __restrict__ rgb_fwd,
+                                                     const float* __restrict__ grad,
+                                                     float* __restrict__ gsig, float* __restrict__ gsh) {
+    const int64_t blk = xcd_swizzle(blockIdx.x, n_blocks);
+    if (blk < 0) return;
+    const int64_t i = blk * kBlock + threadIdx.x;
+    if (i >= n) return;
+    Ray r;
+    if (!ray_setup(tr, o[3 * i], o[3 * i + 1], o[3 * i + 2], d[3 * i], d[3 * i + 1], d[3 * i + 2], r))
+        return;
+    const float g0 = grad[3 * i], g1 = grad[3 * i + 1], g2 = grad[3 * i + 2];
+    if (g0 == 0.0f && g1 == 0.0f && g2 == 0.0f) return;
+    const float C0 = rgb_fwd[3 * i], C1 = rgb_fwd[3 * i + 1], C2 = rgb_fwd[3 * i + 2];
+    float Y[K];
+    sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], Y);
+    const float* sig = static_cast<const float*>(tr.sigma);
+    const char* shb = static_cast<const char*>(tr.sh);
+    const size_t rec_bytes = (size_t)tr.stride * sizeof(float);
+    const float stopT = op.stop_T;
+    float Tl = 1.0f, P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
+    march(tr, r, op.max_steps, [&](int leaf, float delta) -> bool {
+        const float s = fmaxf(load_sigma(sig, leaf), 0.0f);
+        if (!(s > 0.0f)) return false;  // no density: zero weight, and dC/dsigma is masked
+        float rec[NL];
+        load_record<float, NL, VEC>(shb + (size_t)leaf * rec_bytes, rec);
+        const float ex = __expf(-(s * delta));
+        const float w = Tl * (1.0f - ex);
+        const float Tn = Tl * ex;
+        const float c0 = sigmoid(dot_channel<K>(rec, Y));
+        const float c1 = sigmoid(dot_channel<K>(rec + K, Y));
+        const float c2 = sigmoid(dot_channel<K>(rec + 2 * K, Y));
+        P0 = fmaf(w, c0, P0);
+        P1 = fmaf(w, c1, P1);
+        P2 = fmaf(w, c2, P2);
+        // dC/dsigma_i = delta_i (c_i T_{i+1} - (C - P_i)), summed over channels
+        float gs = g0 * (c0 * Tn - (C0 - P0));
+        gs = fmaf(g1, c1 * Tn - (C1 - P1), gs);
+        gs = fmaf(g2, c2 * Tn - (C2 - P2), gs);
+        atomicAdd(gsig + leaf, gs * delta);
+        // dC/dk = w c (1 - c) Y
+        float* gk = gsh + (size_t)leaf * tr.stride;
+        const float z0 = g0 * w * c0 * (1.0f - c0);
+        const float z1 = g1 * w * c1 * (1.0f - c1);
+        const float z2 = g2 * w * c2 * (1.0f - c2);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            atomicAdd(gk + k, z0 * Y[k]);
+            atomicAdd(gk + K + k, z1 * Y[k]);
+            atomicAdd(gk + 2 * K + k, z2 * Y[k]);
+        }
+        Tl = Tn;
+        return Tl < stopT;
+    });
+}
+
+inline int64_t grid_for(int64_t n_blocks) { return 8 * ((n_blocks + 7) / 8); }
+
+// Record-load plan: "fast" loads the padded record with the widest vectors,
+// "generic" uses dword loads of exactly the record (rounded to whole dwords).
+template <typename T, int K>
+struct Plan {
+    static constexpr int NE = 3 * K;
+    static constexpr int FAST_VEC = (sizeof(T) == 4) ? 16 : ((NE * 2) % 16 == 0 ? 16 : 8);
+    static constexpr int FAST_NL = ((NE * (int)sizeof(T) + FAST_VEC - 1) / FAST_VEC) * FAST_VEC / (int)sizeof(T);
+    static constexpr int GEN_NL = (sizeof(T) == 2) ? ((NE + 1) / 2) * 2 : NE;
+};
+
+template <typename T, int K>
+bool use_fast(const po_tree* t) {
+    using P = Plan<T, K>;
+    return t->vec_bytes >= P::FAST_VEC && t->stride >= P::FAST_NL &&
+           ((size_t)t->stride * sizeof(T)) % P::FAST_VEC == 0;
+}
+
+template <typename T, int K>
+hipError_t rays_t(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op, float* rgb,
+                  float* aux, hipStream_t s) {
+    using P = Plan<T, K>;
+    const int64_t nb = (n + kBlock - 1) / kBlock;
+    dim3 grid((unsigned)grid_for(nb)), block(kBlock);
+    if (use_fast<T, K>(t))
+        hipLaunchKernelGGL((k_render_rays<T, K, P::FAST_VEC, P::FAST_NL>), grid, block, 0, s, t->kt, n, nb, o,
+                           d, op, rgb, aux);
+    else
+        hipLaunchKernelGGL((k_render_rays<T, K, 4, P::GEN_NL>), grid, block, 0, s, t->kt, n, nb, o, d, op,
+                           rgb, aux);
+    return hipGetLastError();
+}
+
+template <typename T, int K, int MAXJ>
+hipError_t camera_t(const po_tree* t, int n_jobs, KJob* jobs, int n_blocks, hipStream_t s) {
+    using P = Plan<T, K>;
+    KBatch<MAXJ> B;
+    for (int j = 0; j < n_jobs; ++j) B.job[j] = jobs[j];
+    for (int j = n_jobs; j < MAXJ; ++j) B.job[j] = jobs[0];
+    B.n_jobs = n_jobs;
+    B.n_blocks = n_blocks;
+    dim3 grid((unsigned)grid_for(n_blocks)), block(kBlock);
+    if (use_fast<T, K>(t))
+        hipLaunchKernelGGL((k_render_camera<T, K, P::FAST_VEC, P::FAST_NL, MAXJ>), grid, block, 0, s, B);
+    else
+        hipLaunchKernelGGL((k_render_camera<T, K, 4, P::GEN_NL, MAXJ>), grid, block, 0, s, B);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t backward_t(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
+                      const float* rgb_fwd, const float* grad, float* gsig, float* gsh, hipStream_t s) {
+    using P = Plan<float, K>;
+    const int64_t nb = (n + kBlock - 1) / kBlock;
+    dim3 grid((unsigned)grid_for(nb)), block(kBlock);
+    if (use_fast<float, K>(t))
+        hipLaunchKernelGGL((k_backward<K, P::FAST_VEC, P::FAST_NL>), grid, block, 0, s, t->kt, n, nb, o, d, op,
+                           rgb_fwd, grad, gsig, gsh);
+    else
+        hipLaunchKernelGGL((k_backward<K, 4, P::GEN_NL>), grid, block, 0, s, t->kt, n, nb, o, d, op, rgb_fwd,
+                           grad, gsig, gsh);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define PO_DISPATCH_K(K_, EXPR)                      \
+    switch (K_) {                                    \
+        case 1: { constexpr int KK = 1; return EXPR; }   \
+        case 4: { constexpr int KK = 4; return EXPR; }   \
+        case 9: { constexpr int KK = 9; return EXPR; }   \
+        case 16: { constexpr int KK = 16; return EXPR; } \
+        default: return hipErrorInvalidValue;        \
+    }
+
+hipError_t po_launch_rays(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
+                          float* rgb, float* aux, hipStream_t s) {
+    if (t->desc.dtype == PO_F32) {
+        PO_DISPATCH_K(t->K, (rays_t<float, KK>(t, n, o, d, op, rgb, aux, s)));
+    } else {
+        PO_DISPATCH_K(t->K, (rays_t<__half, KK>(t, n, o, d, op, rgb, aux, s)));
+    }
+}
+
+hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, hipStream_t s) {
+    if (n_jobs == 1) {
+        if (first->desc.dtype == PO_F32) {
+            PO_DISPATCH_K(first->K, (camera_t<float, KK, 1>(first, n_jobs, jobs, n_blocks, s)));
+        } else {
+            PO_DISPATCH_K(first->K, (camera_t<__half, KK, 1>(first, n_jobs, jobs, n_blocks, s)));
+        }
+    }
+    if (first->desc.dtype == PO_F32) {
+        PO_DISPATCH_K(first->K, (camera_t<float, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, s)));
+    } else {
+        PO_DISPATCH_K(first->K, (camera_t<__half, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, s)));
+    }
+}
+
+hipError_t po_launch_backward(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
+                              const float* rgb_fwd, const float* grad, float* gsig, float* gsh, hipStream_t s) {
+    PO_DISPATCH_K(t->K, (backward_t<KK>(t, n, o, d, op, rgb_fwd, grad, gsig, gsh, s)));
+}
+
+hipError_t po_read_device_errors(unsigned long long* out) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    return hipMemcpyFromSymbol(out, HIP_SYMBOL(g_po_errors), sizeof(unsigned long long), 0,
+                               hipMemcpyDeviceToHost);
+}
+
+hipError_t po_reset_device_errors() {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    const unsigned long long zero = 0ull;
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_po_errors), &zero, sizeof(zero), 0, hipMemcpyHostToDevice);
+}
+
+int po_plan_id(const po_tree* t) {
+    bool fast = false;
+    if (t->desc.dtype == PO_F32) {
+        switch (t->K) {
+            case 1: fast = use_fast<float, 1>(t); break;
+            case 4: fast = use_fast<float, 4>(t); break;
+            case 9: fast = use_fast<float, 9>(t); break;
+            case 16: fast = use_fast<float, 16>(t); break;
+        }
+    } else {
+        switch (t->K) {
+            case 1: fast = use_fast<__half, 1>(t); break;
+            case 4: fast = use_fast<__half, 4>(t); break;
+            case 9: fast = use_fast<__half, 9>(t); break;
+            case 16: fast = use_fast<__half, 16>(t); break;
+        }
+    }
+    return (t->desc.dtype * 64 + t->K) * 2 + (fast ? 1 : 0);
+}

@@ -1,0 +1,194 @@
+"""Rendering and gradient calls (thin wrappers over the C ABI) and the
+torch.autograd.Function used for direct octree optimisation (Sec. 4.3)."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def make_opts(bg=(1.0, 1.0, 1.0), stop_T=1e-4, max_steps=0, aux=False) -> L.po_render_opts:
+    o = L.po_render_opts()
+    for k in range(3):
+        o.bg[k] = float(bg[k])
+    o.stop_T = float(stop_T)
+    o.max_steps = int(max_steps)
+    o.flags = L.PO_OUT_AUX if aux else 0
+    return o
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _rays3(t, name):
+    torch = _torch()
+    if not (t.is_cuda and t.dtype == torch.float32 and t.dim() == 2 and t.shape[1] == 3 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 (n, 3) device tensor")
+
+
+@dataclass
+class Camera:
+    """Pinhole camera: c2w row-major 3x4 (right, up, backward, position)."""
+    c2w: np.ndarray
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+
+    def to_c(self) -> L.po_camera:
+        c = L.po_camera()
+        m = np.asarray(self.c2w, np.float32).reshape(12)
+        for i in range(12):
+            c.c2w[i] = float(m[i])
+        c.width, c.height = int(self.width), int(self.height)
+        c.fx, c.fy, c.cx, c.cy = float(self.fx), float(self.fy), float(self.cx), float(self.cy)
+        return c
+
+    @property
+    def n_tiles(self) -> int:
+        return ((self.width + L.PO_TILE - 1) // L.PO_TILE) * ((self.height + L.PO_TILE - 1) // L.PO_TILE)
+
+
+def render_rays(tree, origins, dirs, bg=(1.0, 1.0, 1.0), stop_T=1e-4, aux=False, max_steps=0, out=None,
+                aux_out=None, stream=None):
+    """Colours (n, 3) of rays (origins, dirs: float32 (n, 3) device tensors)."""
+    torch = _torch()
+    _rays3(origins, "origins")
+    _rays3(dirs, "dirs")
+    n = origins.shape[0]
+    if dirs.shape[0] != n:
+        raise ValueError("origins and dirs differ in length")
+    rgb = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=origins.device)
+    a = None
+    if aux:
+        a = aux_out if aux_out is not None else torch.empty((n, 3), dtype=torch.float32, device=origins.device)
+    opts = make_opts(bg, stop_T, max_steps, aux)
+    L.call("po_render_rays", tree.handle, n, origins.data_ptr(), dirs.data_ptr(), ctypes.byref(opts),
+           rgb.data_ptr(), a.data_ptr() if a is not None else None, _stream_ptr(stream))
+    return (rgb, a) if aux else rgb
+
+
+def render_camera(tree, cam: Camera, bg=(1.0, 1.0, 1.0), stop_T=1e-4, aux=False, max_steps=0, out=None,
+                  aux_out=None, stream=None, device="cuda"):
+    """Image (H, W, 3) of a camera."""
+    torch = _torch()
+    shape = (cam.height, cam.width, 3)
+    img = out if out is not None else torch.empty(shape, dtype=torch.float32, device=device)
+    a = None
+    if aux:
+        a = aux_out if aux_out is not None else torch.empty(shape, dtype=torch.float32, device=device)
+    opts = make_opts(bg, stop_T, max_steps, aux)
+    c = cam.to_c()
+    L.call("po_render_camera", tree.handle, ctypes.byref(c), ctypes.byref(opts), img.data_ptr(),
+           a.data_ptr() if a is not None else None, _stream_ptr(stream))
+    return (img, a) if aux else img
+
+
+def render_rays_backward(tree, origins, dirs, rgb_fwd, grad_rgb, bg=(1.0, 1.0, 1.0), stop_T=1e-4, max_steps=0,
+                         grad_sigma=None, grad_sh=None, stream=None):
+    """Accumulates dL/dsigma (n_leaves,) and dL/dsh (n_leaves, stride); returns both."""
+    torch = _torch()
+    _rays3(origins, "origins")
+    _rays3(dirs, "dirs")
+    _rays3(rgb_fwd, "rgb_fwd")
+    _rays3(grad_rgb, "grad_rgb")
+    if grad_sigma is None:
+        grad_sigma = torch.zeros_like(tree.sigma, dtype=torch.float32)
+    if grad_sh is None:
+        grad_sh = torch.zeros_like(tree.sh, dtype=torch.float32)
+    opts = make_opts(bg, stop_T, max_steps)
+    L.call("po_render_rays_backward", tree.handle, origins.shape[0], origins.data_ptr(), dirs.data_ptr(),
+           ctypes.byref(opts), rgb_fwd.data_ptr(), grad_rgb.data_ptr(), grad_sigma.data_ptr(), grad_sh.data_ptr(),
+           _stream_ptr(stream))
+    return grad_sigma, grad_sh
+
+
+class RenderRaysFn:
+    """torch.autograd.Function over (sigma, sh) of a float32 tree.
+
+    Forward renders the rays (the first pass of App. B.3's Remark, storing the
+    full colour C); backward replays the walk and accumulates the leaf
+    gradients with atomics (the second pass)."""
+
+    _fn = None
+
+    @classmethod
+    def get(cls):
+        if cls._fn is None:
+            torch = _torch()
+
+            class _F(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, sigma, sh, tree, origins, dirs, bg, stop_T):
+                    if sigma.data_ptr() != tree.sigma.data_ptr() or sh.data_ptr() != tree.sh.data_ptr():
+                        raise ValueError("sigma/sh must be the tensors the tree is bound to")
+                    rgb = render_rays(tree, origins, dirs, bg=bg, stop_T=stop_T)
+                    ctx.tree, ctx.bg, ctx.stop_T = tree, bg, stop_T
+                    ctx.save_for_backward(origins, dirs, rgb)
+                    return rgb
+
+                @staticmethod
+                def backward(ctx, grad_rgb):
+                    origins, dirs, rgb = ctx.saved_tensors
+                    gs, gh = render_rays_backward(ctx.tree, origins, dirs, rgb, grad_rgb.contiguous(), bg=ctx.bg,
+                                                  stop_T=ctx.stop_T)
+                    return gs, gh, None, None, None, None, None
+
+            cls._fn = _F
+        return cls._fn
+
+
+def render_rays_differentiable(tree, origins, dirs, bg=(1.0, 1.0, 1.0), stop_T=1e-4):
+    """Differentiable render: gradients flow to tree.sigma and tree.sh
+    (set requires_grad on them first)."""
+    return RenderRaysFn.get().apply(tree.sigma, tree.sh, tree, origins, dirs, tuple(bg), float(stop_T))
+
+
+@dataclass
+class Job:
+    tree: object
+    cam: Camera
+    out: object            # (H, W, 3) float32 device tensor
+    tile_begin: int = 0
+    tile_end: int = -1     # -1: to the last tile
+    bg: tuple = (1.0, 1.0, 1.0)
+    stop_T: float = 1e-4
+    aux_out: object = None
+
+
+def render_batch(jobs, stream=None) -> None:
+    """Renders up to 16 camera jobs (any trees, any sizes, tile sub-ranges)."""
+    arr = (L.po_job * max(1, len(jobs)))()
+    for i, j in enumerate(jobs):
+        arr[i].tree = j.tree.handle.value
+        arr[i].cam = j.cam.to_c()
+        arr[i].opts = make_opts(j.bg, j.stop_T, 0, j.aux_out is not None)
+        arr[i].d_rgb = j.out.data_ptr()
+        arr[i].d_aux = j.aux_out.data_ptr() if j.aux_out is not None else None
+        arr[i].tile_begin = int(j.tile_begin)
+        arr[i].tile_end = int(j.cam.n_tiles if j.tile_end < 0 else j.tile_end)
+    L.call("po_render_batch", len(jobs), arr, _stream_ptr(stream))
+
+
+def device_errors() -> int:
+    v = ctypes.c_int64()
+    L.call("po_device_errors", ctypes.byref(v))
+    return int(v.value)
+
+
+def reset_device_errors() -> None:
+    L.call("po_device_errors_reset")

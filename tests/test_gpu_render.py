@@ -1,0 +1,277 @@
+"""GPU forward renders (HIP kernels through the C ABI) against the FP64 oracle.
+
+Tolerance: 1e-4 absolute per channel for float32 leaves, the bar the
+renderer is held to; float16 leaves are compared with the oracle evaluated on
+the decoded float16 values (same 1e-4) and, for the quantisation error, with
+the oracle on the float32 values (2e-3).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_14024_amd import scenes
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def po():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2103_14024_amd as po
+
+    po.reset_device_errors()
+    return po
+
+
+def _announce(msg):
+    print(f"[gpu] {msg}", file=sys.stderr, flush=True)
+
+
+def _cam(po, pose, W, H, fov=40.0):
+    fx, fy, cx, cy = scenes.intrinsics(W, H, fov)
+    return po.Camera(pose, W, H, fx, fy, cx, cy)
+
+
+def _otree(s, sigma=None, sh=None):
+    return oracle.OracleTree(s["depth"], s["sh_degree"], s["center"], s["half"], s["cells"],
+                             s["sigma"] if sigma is None else sigma, s["sh"] if sh is None else sh)
+
+
+def _dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).cuda()
+
+
+def test_small_scene_camera(po):
+    _announce("small scene 64x64 camera")
+    s = scenes.scene_small()
+    tree = po.Tree.from_scene(s)
+    pose = scenes.small_pose()
+    cam = _cam(po, pose, 64, 64)
+    img, aux = po.render_camera(tree, cam, stop_T=1e-4, aux=True)
+    img, aux = img.cpu().numpy(), aux.cpu().numpy()
+    ref, T, ns = _otree(s).render_camera(pose, 64, 64, cam.fx, cam.fy, cam.cx, cam.cy, gamma=1e-4)
+    err = np.abs(img - ref)
+    _announce(f"small scene max err {err.max():.3e} mean {err.mean():.3e}")
+    assert err.max() <= TOL
+    assert np.abs(aux[..., 0] - T).max() <= TOL
+    # sample counts agree except where a corner-clipped segment rounds to zero length
+    assert np.mean(aux[..., 1] == ns) > 0.99 and np.abs(aux[..., 1] - ns).max() <= 2
+    assert ns.max() > 0
+    assert po.device_errors() == 0
+
+
+@pytest.mark.parametrize("W,H", [(67, 45), (1, 1), (17, 1), (16, 33)])
+def test_ragged_image_sizes(po, W, H):
+    _announce(f"ragged camera {W}x{H}")
+    s = scenes.scene_small()
+    tree = po.Tree.from_scene(s)
+    pose = scenes.hemisphere_poses(1, 3.0, 5)[0]
+    cam = _cam(po, pose, W, H, 60.0)
+    img = po.render_camera(tree, cam, stop_T=1e-4).cpu().numpy()
+    ref, _, _ = _otree(s).render_camera(pose, W, H, cam.fx, cam.fy, cam.cx, cam.cy, gamma=1e-4)
+    assert img.shape == (H, W, 3)
+    assert np.abs(img - ref).max() <= TOL
+
+
+def _ray_set(n_free=4096 + 37):
+    o1, d1 = scenes.random_rays(n_free, 11)
+    o2, d2 = scenes.inside_rays(300, 12)
+    # axis-aligned rays, some lying in grid planes, and rays with zero components
+    o3 = np.array([[-3.0, 0.0, 0.25], [0.5, -3.0, -0.5], [0.0, 0.0, 3.0], [-2.0, 0.5, 0.75], [0.1, 0.2, -4.0],
+                   [-3.0, -0.125, 0.0625], [3.0, 0.3, 0.3], [0.3, 3.0, 0.2]], np.float32)
+    d3 = np.array([[1, 0, 0], [0, 1, 0], [0, 0, -1], [1, 0, 0], [0, 0, 1], [1, 0.0, 0.0], [-1, 0.1, 0],
+                   [0, -1, 0.05]], np.float32)
+    return np.concatenate([o1, o2, o3]), np.concatenate([d1, d2, d3])
+
+
+@pytest.mark.parametrize("kind", ["small", "mixed5", "mixed7"])
+def test_rays_parity(po, kind):
+    _announce(f"rays parity {kind}")
+    if kind == "small":
+        s = scenes.scene_small()
+    else:
+        depth = int(kind[-1])
+        cells = scenes.random_tree_cells(depth, depth, p_split=0.55, p_leaf=0.5)
+        sigma, sh = scenes.leaf_values(len(cells), 3, 40 + depth, mu=1.0)
+        sigma[::9] *= -1
+        s = dict(depth=depth, sh_degree=3, center=(0.0, 0.0, 0.0), half=1.0, cells=cells, sigma=sigma, sh=sh)
+    tree = po.Tree.from_scene(s)
+    o, d = _ray_set()
+    rgb, aux = po.render_rays(tree, _dev(o), _dev(d), bg=(0.2, 0.5, 0.9), stop_T=1e-4, aux=True)
+    ref, T, ns, _ = _otree(s).render_rays(o, d, bg=(0.2, 0.5, 0.9), gamma=1e-4)
+    err = np.abs(rgb.cpu().numpy() - ref)
+    _announce(f"{kind}: leaves {len(s['cells'])} max err {err.max():.3e}")
+    assert err.max() <= TOL
+    assert np.abs(aux.cpu().numpy()[:, 0] - T).max() <= TOL
+    assert po.device_errors() == 0
+
+
+def test_non_unit_box_and_deep_tree(po):
+    _announce("deep tree, off-centre box")
+    depth = 12
+    rng = np.random.default_rng(3)
+    # a few deep leaves plus coarse ones in a box of half-size 2.5 centred off the origin
+    g = np.arange(2000, 2016)
+    fine = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    cells = np.concatenate([np.column_stack([np.full(len(fine), depth), fine]),
+                            np.array([[2, 0, 0, 0], [3, 7, 7, 7], [2, 0, 3, 0]])]).astype(np.int32)
+    sigma, sh = scenes.leaf_values(len(cells), 2, 5, mu=3.0)
+    s = dict(depth=depth, sh_degree=2, center=(0.5, -0.25, 1.0), half=2.5, cells=cells, sigma=sigma, sh=sh)
+    tree = po.Tree.from_scene(s)
+    c = np.array(s["center"])
+    o, d = scenes.random_rays(3000, 21, radius=8.0, spread=2.7)
+    o = o + c.astype(np.float32)
+    # aim a third of the rays at the fine cluster
+    tgt = c - 2.5 + (rng.uniform(2000, 2016, (1000, 3)) / 4096.0) * 5.0
+    d[:1000] = (tgt - o[:1000]).astype(np.float32)
+    rgb = po.render_rays(tree, _dev(o), _dev(d), stop_T=1e-4)
+    ref, _, ns, _ = _otree(s).render_rays(o, d, gamma=1e-4)
+    assert ns[:1000].max() >= 16
+    assert np.abs(rgb.cpu().numpy() - ref).max() <= TOL
+    assert po.device_errors() == 0
+
+
+def test_invariants(po):
+    _announce("invariants")
+    s = scenes.scene_small()
+    o, d = _ray_set(2000)
+    # empty tree renders the background exactly
+    e = dict(s, cells=np.zeros((0, 4), np.int32), sigma=np.zeros(0, np.float32),
+             sh=np.zeros((0, 3, 9), np.float32))
+    rgb = po.render_rays(po.Tree.from_scene(e), _dev(o), _dev(d), bg=(0.1, 0.2, 0.3)).cpu().numpy()
+    assert np.all(rgb == np.array([0.1, 0.2, 0.3], np.float32))
+    # every colour equal to the background: the image is the background
+    bg = np.array([0.3, 0.6, 0.8])
+    sh = np.zeros_like(s["sh"])
+    sh[:, :, 0] = (np.log(bg / (1 - bg)) / (0.5 / math.sqrt(math.pi)))[None, :]
+    rgb = po.render_rays(po.Tree.from_scene(dict(s, sh=sh)), _dev(o), _dev(d), bg=tuple(bg)).cpu().numpy()
+    assert np.abs(rgb - bg).max() < 1e-5
+    # subdividing leaves into identical children leaves the render unchanged
+    tree = po.Tree.from_scene(s)
+    c2, s2, h2 = scenes.subdivide(s["cells"], s["sigma"], s["sh"], np.arange(0, len(s["cells"]), 2))
+    tree2 = po.Tree.from_scene(dict(s, depth=6, cells=c2, sigma=s2, sh=h2))
+    a = po.render_rays(tree, _dev(o), _dev(d), stop_T=0.0).cpu().numpy()
+    b = po.render_rays(tree2, _dev(o), _dev(d), stop_T=0.0).cpu().numpy()
+    assert np.abs(a - b).max() < 1e-5
+    # early stop changes no channel by more than gamma
+    for g in (1e-2, 1e-3):
+        c = po.render_rays(tree, _dev(o), _dev(d), stop_T=g).cpu().numpy()
+        assert np.abs(c - a).max() <= g + 1e-6
+    # affine in the background: C(bg=1) - C(bg=0) = T
+    c1, aux = po.render_rays(tree, _dev(o), _dev(d), bg=(1, 1, 1), aux=True)
+    c0 = po.render_rays(tree, _dev(o), _dev(d), bg=(0, 0, 0))
+    diff = (c1 - c0).cpu().numpy() - aux.cpu().numpy()[:, :1]
+    assert np.abs(diff).max() < 1e-6
+
+
+def test_zero_rays_and_degenerate_directions(po):
+    import torch
+
+    s = scenes.scene_small()
+    tree = po.Tree.from_scene(s)
+    z = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    assert po.render_rays(tree, z, z).shape == (0, 3)
+    o = _dev([[0.0, 0.0, -3.0], [0.0, 0.0, -3.0], [np.nan, 0, 0]])
+    d = _dev([[0.0, 0.0, 0.0], [np.nan, 0.0, 1.0], [0, 0, 1]])
+    rgb = po.render_rays(tree, o, d, bg=(0.25, 0.5, 0.75)).cpu().numpy()
+    assert np.all(rgb == np.array([0.25, 0.5, 0.75], np.float32))
+
+
+def test_device_error_counter(po):
+    """A malformed child array on the device is read safely (out-of-range
+    entries are treated as empty) and counted; a tiny step cap is counted."""
+    import torch
+
+    _announce("device error counter")
+    s = scenes.scene_small()
+    tree = po.Tree.from_scene(s)
+    o, d = _ray_set(500)
+    po.reset_device_errors()
+    po.render_rays(tree, _dev(o), _dev(d), max_steps=2)
+    torch.cuda.synchronize()
+    assert po.device_errors() > 0
+    po.reset_device_errors()
+    child = tree.child.clone()
+    child[child > 0] = child.shape[0] + 100     # every internal reference out of range
+    bad = po.Tree(s["depth"], s["sh_degree"], child, tree.sigma, tree.sh)
+    rgb = po.render_rays(bad, _dev(o), _dev(d), bg=(0.5, 0.5, 0.5)).cpu().numpy()
+    assert po.device_errors() > 0
+    assert np.isfinite(rgb).all()
+    po.reset_device_errors()
+    assert po.device_errors() == 0
+
+
+def test_fp16_leaves(po):
+    _announce("fp16 leaves")
+    s = scenes.scene_small()
+    o, d = _ray_set(3000)
+    t16 = po.Tree.from_scene(s, dtype="f16")
+    sig16, sh16 = t16.leaf_values()
+    rgb = po.render_rays(t16, _dev(o), _dev(d), stop_T=1e-4).cpu().numpy()
+    ref16, _, _, _ = _otree(s, sig16, sh16).render_rays(o, d, gamma=1e-4)
+    ref32, _, _, _ = _otree(s).render_rays(o, d, gamma=1e-4)
+    assert np.abs(rgb - ref16).max() <= TOL
+    q = np.abs(rgb - ref32)
+    _announce(f"fp16 quantisation error max {q.max():.3e} mean {q.mean():.3e}")
+    assert q.max() <= 2e-3
+    # camera path with fp16 leaves and degree 3 / degree 1 / degree 0 trees
+    for deg in (0, 1, 3):
+        cells = s["cells"]
+        sig, sh = scenes.leaf_values(len(cells), deg, 9 + deg)
+        sd = dict(s, sh_degree=deg, sigma=sig, sh=sh)
+        for dt in ("f32", "f16"):
+            tr = po.Tree.from_scene(sd, dtype=dt)
+            sv, hv = tr.leaf_values()
+            pose = scenes.small_pose()
+            cam = _cam(po, pose, 40, 24)
+            img = po.render_camera(tr, cam).cpu().numpy()
+            ref, _, _ = _otree(sd, sv, hv).render_camera(pose, 40, 24, cam.fx, cam.fy, cam.cx, cam.cy, gamma=1e-4)
+            assert np.abs(img - ref).max() <= TOL, (deg, dt)
+
+
+def test_unpadded_record_layout(po):
+    """Records packed at exactly 3K elements (dword loads) render like padded ones."""
+    s = scenes.scene_small()
+    o, d = _ray_set(1000)
+    a = po.render_rays(po.Tree.from_scene(s), _dev(o), _dev(d)).cpu().numpy()
+    b = po.render_rays(po.Tree.from_scene(s, stride=27), _dev(o), _dev(d)).cpu().numpy()
+    c = po.render_rays(po.Tree.from_scene(s, stride=40), _dev(o), _dev(d)).cpu().numpy()
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_batch_matches_single_renders(po):
+    """Jobs of several trees, sizes and tile ranges in one call give the same
+    pixels as separate render_camera calls (bit-identical)."""
+    import torch
+
+    _announce("batch")
+    s = scenes.scene_small()
+    trees = [po.Tree.from_scene(s), po.Tree.from_scene(s, dtype="f16"),
+             po.Tree.from_scene(dict(s, sh_degree=3, sh=scenes.leaf_values(len(s["cells"]), 3, 4)[1]))]
+    poses = scenes.hemisphere_poses(6, 4.0, 8)
+    sizes = [(64, 64), (50, 30), (33, 17), (16, 16), (100, 20), (7, 9)]
+    jobs, singles = [], []
+    for i, (W, H) in enumerate(sizes):
+        tr = trees[i % 3]
+        cam = _cam(po, poses[i], W, H)
+        out = torch.full((H, W, 3), -1.0, device="cuda")
+        nt = cam.n_tiles
+        # split the first job's tiles across two jobs
+        if i == 0:
+            jobs.append(po.Job(tr, cam, out, 0, nt // 2))
+            jobs.append(po.Job(tr, cam, out, nt // 2, nt))
+        else:
+            jobs.append(po.Job(tr, cam, out))
+        singles.append((tr, cam, out))
+    po.render_batch(jobs)
+    for tr, cam, out in singles:
+        ref = po.render_camera(tr, cam)
+        assert torch.equal(out, ref)
