@@ -70,18 +70,24 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float (&Y)[K
 __device__ __forceinline__ float load_sigma(const float* p, int i) { return p[i]; }
 __device__ __forceinline__ float load_sigma(const __half* p, int i) { return __half2float(p[i]); }
 
-// Loads NL elements of one SH record at `base` using VEC-byte loads (16, 8 or
-// 4; `base` is VEC-aligned) followed by dword loads and, for an odd number
-// of halves, one 2-byte load.  The host guarantees NL elements lie inside
-// the record (NL <= stride).
+// Number of 32-bit words holding NL elements of type T.
+template <typename T, int NL>
+struct Words {
+    static constexpr int NB = NL * (int)sizeof(T);
+    static constexpr int N = (NB + 3) / 4;
+};
+
+// Loads NL elements of one SH record at `base` as raw 32-bit words using
+// VEC-byte loads (16, 8 or 4; `base` is VEC-aligned), then dword loads and,
+// for an odd number of halves, one 2-byte load.  The host guarantees the NL
+// elements lie inside the record (NL <= stride).  The loads are only issued
+// here; the words are consumed later, so their latency can overlap other work.
 template <typename T, int NL, int VEC>
-__device__ __forceinline__ void load_record(const char* __restrict__ base, float (&out)[NL]) {
-    constexpr int NB = NL * (int)sizeof(T);
-    constexpr int NW = (NB + 3) / 4;
+__device__ __forceinline__ void load_words(const char* __restrict__ base, uint32_t (&w)[Words<T, NL>::N]) {
+    constexpr int NB = Words<T, NL>::NB;
     constexpr int NV = NB / VEC;
     constexpr int DONE = NV * VEC / 4;
     constexpr int FULLW = NB / 4;
-    uint32_t w[NW];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         if constexpr (VEC == 16) {
@@ -101,14 +107,16 @@ __device__ __forceinline__ void load_record(const char* __restrict__ base, float
 #pragma unroll
     for (int i = DONE; i < FULLW; ++i) w[i] = *reinterpret_cast<const uint32_t*>(base + 4 * i);
     if constexpr (NB % 4 != 0) w[FULLW] = *reinterpret_cast<const uint16_t*>(base + 4 * FULLW);
-#pragma unroll
-    for (int i = 0; i < NL; ++i) {
-        if constexpr (sizeof(T) == 4) {
-            out[i] = __uint_as_float(w[i]);
-        } else {
-            const uint32_t h = (i & 1) ? (w[i >> 1] >> 16) : (w[i >> 1] & 0xffffu);
-            out[i] = __half2float(__ushort_as_half((unsigned short)h));
-        }
+}
+
+// Element i of a record held as raw words, widened to float.
+template <typename T, int NW>
+__device__ __forceinline__ float word_elem(const uint32_t (&w)[NW], int i) {
+    if constexpr (sizeof(T) == 4) {
+        return __uint_as_float(w[i]);
+    } else {
+        const uint32_t h = (i & 1) ? (w[i >> 1] >> 16) : (w[i >> 1] & 0xffffu);
+        return __half2float(__ushort_as_half((unsigned short)h));
     }
 }
 
@@ -135,10 +143,7 @@ struct Ray {
     double s;      // current parameter
 };
 
-__device__ __forceinline__ bool ray_setup(const KTree& tr, float ox, float oy, float oz, float dx,
-                                          float dy, float dz, Ray& r) {
-    const double d[3] = {(double)dx, (double)dy, (double)dz};
-    const double o[3] = {(double)ox, (double)oy, (double)oz};
+__device__ __forceinline__ bool ray_setup(const KTree& tr, const double (&o)[3], const double (&d)[3], Ray& r) {
     const double len2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     if (!(len2 > 0.0) || !(len2 < 1e300)) return false;
     r.len = sqrt(len2);
@@ -173,18 +178,33 @@ __device__ __forceinline__ bool ray_setup(const KTree& tr, float ox, float oy, f
     return true;
 }
 
-// Walks the segments of a ray.  For every data leaf crossed over a positive
-// length, calls on_sample(leaf, delta) with delta in world units; a true
-// return stops the walk.  Returns the number of cells visited.
-template <class OnSample>
-__device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, OnSample&& on_sample) {
+// Walks the segments of a ray.  Data leaves crossed over a positive length
+// go through a two-stage sampler: smp.issue(leaf, delta) starts the loads of
+// the leaf's density and SH record, and smp.consume() -- called one step
+// later, after the next cell's descent -- shades and composites it and
+// returns true to stop the walk.  The gather of one sample thus overlaps the
+// tree loads of the next step.  The samples, their order and the stop point
+// are those of the plain front-to-back walk.  Returns the number of cells
+// visited.
+//
+// stk is this lane's column of a [level][kBlock] node stack in LDS: the
+// descent records the node it passes at every level, and after a step the
+// next descent restarts from the deepest ancestor shared by the old and the
+// new cell (the level of the highest differing coordinate bit) instead of
+// the root, so a step costs one or two dependent loads instead of ~D.
+template <class Sampler>
+__device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int* __restrict__ stk,
+                                     Sampler& smp) {
     const int D = tr.depth;
     const int N = 1 << D;
     int steps = 0;
+    int node = 0, L = 0;
+    bool pending = false;
     while (true) {
-        // descend from the root to the leaf (data or empty) holding cell c
-        int node = 0, L = 0, e;
+        // descend from (node, level L) to the leaf (data or empty) holding cell c
+        int e;
         while (true) {
+            stk[L * kBlock] = node;
             const int sft = D - 1 - L;
             const int oct = (((r.c[0] >> sft) & 1) << 2) | (((r.c[1] >> sft) & 1) << 1) | ((r.c[2] >> sft) & 1);
             e = __ldg(tr.child + ((size_t)node * 8 + oct));
@@ -220,9 +240,16 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, OnS
         }
         const double se = fmax(fmin(fmin(sk[0], sk[1]), sk[2]), r.s);
         ++steps;
+        if (pending) {
+            pending = false;
+            if (smp.consume()) return steps;
+        }
         if (leaf >= 0) {
             const float delta = (float)((se - r.s) * r.len);
-            if (delta > 0.0f && on_sample(leaf, delta)) break;
+            if (delta > 0.0f) {
+                smp.issue(leaf, delta);
+                pending = true;
+            }
         }
         // move across the exit face(s)
         bool out = false;
@@ -243,64 +270,89 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, OnS
         }
         r.s = se;
         if (out) break;
-        r.c[0] = nc[0];
-        r.c[1] = nc[1];
-        r.c[2] = nc[2];
         if (steps >= max_steps) {
             atomicAdd(&g_po_errors, 1ull);
             break;
         }
+        // deepest common ancestor: the cells agree on the coordinate bits above
+        // the highest differing one
+        const int diff = (r.c[0] ^ nc[0]) | (r.c[1] ^ nc[1]) | (r.c[2] ^ nc[2]);
+        L = D - 32 + __clz(diff);
+        node = stk[L * kBlock];
+        r.c[0] = nc[0];
+        r.c[1] = nc[1];
+        r.c[2] = nc[2];
     }
+    if (pending) smp.consume();
     return steps;
 }
 
-template <int K>
-__device__ __forceinline__ float dot_channel(const float* rec, const float (&Y)[K]) {
-    float z = rec[0] * Y[0];
+template <typename T, int K, int NW>
+__device__ __forceinline__ float dot_channel(const uint32_t (&w)[NW], int base, const float (&Y)[K]) {
+    float z = word_elem<T>(w, base) * Y[0];
 #pragma unroll
-    for (int k = 1; k < K; ++k) z = fmaf(rec[k], Y[k], z);
+    for (int k = 1; k < K; ++k) z = fmaf(word_elem<T>(w, base + k), Y[k], z);
     return z;
 }
 
+// Forward shading and compositing of the samples of one ray (Sec. 3
+// eqn:quad, Sec. 4.1 colour, App. B.3 clamp of the raw density).
+template <typename T, int K, int VEC, int NL>
+struct FwdSampler {
+    static constexpr int NW = Words<T, NL>::N;
+    const T* sig;
+    const char* shb;
+    size_t rec_bytes;
+    float stopT;
+    float Y[K];
+    float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, Tl = 1.0f;
+    int ns = 0;
+    // in flight
+    float raw, delta;
+    uint32_t w[NW];
+
+    __device__ __forceinline__ void issue(int leaf, float d) {
+        raw = load_sigma(sig, leaf);
+        load_words<T, NL, VEC>(shb + (size_t)leaf * rec_bytes, w);
+        delta = d;
+    }
+    __device__ __forceinline__ bool consume() {
+        ++ns;
+        const float s = fmaxf(raw, 0.0f);
+        if (!(s > 0.0f)) return false;
+        const float ex = __expf(-(s * delta));
+        const float wgt = Tl * (1.0f - ex);
+        c0 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, 0, Y)), c0);
+        c1 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, K, Y)), c1);
+        c2 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, 2 * K, Y)), c2);
+        Tl = Tl * ex;
+        return Tl < stopT;
+    }
+};
+
 // Renders one ray: colour (background included), final T, samples, steps.
 template <typename T, int K, int VEC, int NL>
-__device__ __forceinline__ void render_one(const KTree& tr, const KOpts& op, float ox, float oy, float oz,
-                                           float dx, float dy, float dz, float (&C)[3], float& Tr,
+__device__ __forceinline__ void render_one(const KTree& tr, const KOpts& op, const double (&o)[3],
+                                           const double (&d)[3], int* __restrict__ stk, float (&C)[3], float& Tr,
                                            int& ns, int& steps) {
     C[0] = C[1] = C[2] = 0.0f;
     Tr = 1.0f;
     ns = 0;
     steps = 0;
     Ray r;
-    if (ray_setup(tr, ox, oy, oz, dx, dy, dz, r)) {
-        float Y[K];
-        sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], Y);
-        const T* sig = static_cast<const T*>(tr.sigma);
-        const char* shb = static_cast<const char*>(tr.sh);
-        const size_t rec_bytes = (size_t)tr.stride * sizeof(T);
-        const float stopT = op.stop_T;
-        float Tl = 1.0f;
-        int nsl = 0;
-        float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-        steps = march(tr, r, op.max_steps, [&](int leaf, float delta) -> bool {
-            ++nsl;
-            const float s = fmaxf(load_sigma(sig, leaf), 0.0f);
-            if (!(s > 0.0f)) return false;
-            float rec[NL];
-            load_record<T, NL, VEC>(shb + (size_t)leaf * rec_bytes, rec);
-            const float ex = __expf(-(s * delta));
-            const float w = Tl * (1.0f - ex);
-            c0 = fmaf(w, sigmoid(dot_channel<K>(rec, Y)), c0);
-            c1 = fmaf(w, sigmoid(dot_channel<K>(rec + K, Y)), c1);
-            c2 = fmaf(w, sigmoid(dot_channel<K>(rec + 2 * K, Y)), c2);
-            Tl = Tl * ex;
-            return Tl < stopT;
-        });
-        C[0] = c0;
-        C[1] = c1;
-        C[2] = c2;
-        Tr = Tl;
-        ns = nsl;
+    if (ray_setup(tr, o, d, r)) {
+        FwdSampler<T, K, VEC, NL> smp;
+        smp.sig = static_cast<const T*>(tr.sigma);
+        smp.shb = static_cast<const char*>(tr.sh);
+        smp.rec_bytes = (size_t)tr.stride * sizeof(T);
+        smp.stopT = op.stop_T;
+        sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], smp.Y);
+        steps = march(tr, r, op.max_steps, stk, smp);
+        C[0] = smp.c0;
+        C[1] = smp.c1;
+        C[2] = smp.c2;
+        Tr = smp.Tl;
+        ns = smp.ns;
     }
     C[0] = fmaf(Tr, op.bg[0], C[0]);
     C[1] = fmaf(Tr, op.bg[1], C[1]);
@@ -326,10 +378,12 @@ __global__ __launch_bounds__(kBlock) void k_render_rays(KTree tr, int64_t n, int
     if (blk < 0) return;
     const int64_t i = blk * kBlock + threadIdx.x;
     if (i >= n) return;
+    const double ro[3] = {(double)o[3 * i], (double)o[3 * i + 1], (double)o[3 * i + 2]};
+    const double rd[3] = {(double)d[3 * i], (double)d[3 * i + 1], (double)d[3 * i + 2]};
     float C[3], Tr;
     int ns, steps;
-    render_one<T, K, VEC, NL>(tr, op, o[3 * i], o[3 * i + 1], o[3 * i + 2], d[3 * i], d[3 * i + 1],
-                              d[3 * i + 2], C, Tr, ns, steps);
+    extern __shared__ int po_stack[];
+    render_one<T, K, VEC, NL>(tr, op, ro, rd, po_stack + threadIdx.x, C, Tr, ns, steps);
     rgb[3 * i + 0] = C[0];
     rgb[3 * i + 1] = C[1];
     rgb[3 * i + 2] = C[2];
@@ -365,15 +419,18 @@ __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
     const int px = tx * 16 + (wave & 1) * 8 + (lane & 7);
     const int py = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
     if (px >= J.cam.W || py >= J.cam.H) return;
-    const float x = ((float)px + 0.5f - J.cam.cx) / J.cam.fx;
-    const float y = -(((float)py + 0.5f - J.cam.cy) / J.cam.fy);
+    // pixel-centre ray, evaluated in FP64 like the rest of the ray geometry
+    const double x = ((double)px + 0.5 - (double)J.cam.cx) / (double)J.cam.fx;
+    const double y = -(((double)py + 0.5 - (double)J.cam.cy) / (double)J.cam.fy);
     const float* M = J.cam.c2w;
-    const float dx = M[0] * x + M[1] * y - M[2];
-    const float dy = M[4] * x + M[5] * y - M[6];
-    const float dz = M[8] * x + M[9] * y - M[10];
+    const double rd[3] = {(double)M[0] * x + (double)M[1] * y - (double)M[2],
+                          (double)M[4] * x + (double)M[5] * y - (double)M[6],
+                          (double)M[8] * x + (double)M[9] * y - (double)M[10]};
+    const double ro[3] = {(double)M[3], (double)M[7], (double)M[11]};
     float C[3], Tr;
     int ns, steps;
-    render_one<T, K, VEC, NL>(J.tr, J.op, M[3], M[7], M[11], dx, dy, dz, C, Tr, ns, steps);
+    extern __shared__ int po_stack[];
+    render_one<T, K, VEC, NL>(J.tr, J.op, ro, rd, po_stack + threadIdx.x, C, Tr, ns, steps);
     const size_t p = (size_t)py * J.cam.W + px;
     J.rgb[3 * p + 0] = C[0];
     J.rgb[3 * p + 1] = C[1];
@@ -385,7 +442,67 @@ __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
     }
 }
 
-// Backward (App. B.3): replays the forward walk; C is the forward colour.
+// Gradient of one ray's samples (App. B.3): the forward colour C is the
+// first pass; this second pass keeps the prefix P_i of w_k c_k, so that
+// dC/dsigma_i = delta_i (c_i T_{i+1} - (C - P_i)) (zero where the raw density
+// is <= 0) and dC/dk = w_i c_i (1 - c_i) Y, contracted with dL/dC and added
+// to the leaf gradients with float atomics.
+template <int K, int VEC, int NL>
+struct BwdSampler {
+    static constexpr int NW = Words<float, NL>::N;
+    const float* sig;
+    const char* shb;
+    size_t rec_bytes;
+    int stride;
+    float stopT;
+    float Y[K];
+    float g0, g1, g2, C0, C1, C2;
+    float* gsig;
+    float* gsh;
+    float Tl = 1.0f, P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
+    // in flight
+    int leaf;
+    float raw, delta;
+    uint32_t w[NW];
+
+    __device__ __forceinline__ void issue(int l, float d) {
+        leaf = l;
+        raw = load_sigma(sig, l);
+        load_words<float, NL, VEC>(shb + (size_t)l * rec_bytes, w);
+        delta = d;
+    }
+    __device__ __forceinline__ bool consume() {
+        const float s = fmaxf(raw, 0.0f);
+        if (!(s > 0.0f)) return false;  // no density: zero weight, and dC/dsigma is masked
+        const float ex = __expf(-(s * delta));
+        const float wgt = Tl * (1.0f - ex);
+        const float Tn = Tl * ex;
+        const float c0 = sigmoid(dot_channel<float, K>(w, 0, Y));
+        const float c1 = sigmoid(dot_channel<float, K>(w, K, Y));
+        const float c2 = sigmoid(dot_channel<float, K>(w, 2 * K, Y));
+        P0 = fmaf(wgt, c0, P0);
+        P1 = fmaf(wgt, c1, P1);
+        P2 = fmaf(wgt, c2, P2);
+        float gs = g0 * (c0 * Tn - (C0 - P0));
+        gs = fmaf(g1, c1 * Tn - (C1 - P1), gs);
+        gs = fmaf(g2, c2 * Tn - (C2 - P2), gs);
+        atomicAdd(gsig + leaf, gs * delta);
+        float* gk = gsh + (size_t)leaf * stride;
+        const float z0 = g0 * wgt * c0 * (1.0f - c0);
+        const float z1 = g1 * wgt * c1 * (1.0f - c1);
+        const float z2 = g2 * wgt * c2 * (1.0f - c2);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            atomicAdd(gk + k, z0 * Y[k]);
+            atomicAdd(gk + K + k, z1 * Y[k]);
+            atomicAdd(gk + 2 * K + k, z2 * Y[k]);
+        }
+        Tl = Tn;
+        return Tl < stopT;
+    }
+};
+
+// Backward kernel: replays the forward walk of each ray.
 template <int K, int VEC, int NL>
 __global__ __launch_bounds__(kBlock) void k_backward(KTree tr, int64_t n, int64_t n_blocks,
                                                      const float* __restrict__ o,
@@ -397,55 +514,34 @@ __global__ __launch_bounds__(kBlock) void k_backward(KTree tr, int64_t n, int64_
     if (blk < 0) return;
     const int64_t i = blk * kBlock + threadIdx.x;
     if (i >= n) return;
+    const double ro[3] = {(double)o[3 * i], (double)o[3 * i + 1], (double)o[3 * i + 2]};
+    const double rd[3] = {(double)d[3 * i], (double)d[3 * i + 1], (double)d[3 * i + 2]};
     Ray r;
-    if (!ray_setup(tr, o[3 * i], o[3 * i + 1], o[3 * i + 2], d[3 * i], d[3 * i + 1], d[3 * i + 2], r))
-        return;
-    const float g0 = grad[3 * i], g1 = grad[3 * i + 1], g2 = grad[3 * i + 2];
-    if (g0 == 0.0f && g1 == 0.0f && g2 == 0.0f) return;
-    const float C0 = rgb_fwd[3 * i], C1 = rgb_fwd[3 * i + 1], C2 = rgb_fwd[3 * i + 2];
-    float Y[K];
-    sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], Y);
-    const float* sig = static_cast<const float*>(tr.sigma);
-    const char* shb = static_cast<const char*>(tr.sh);
-    const size_t rec_bytes = (size_t)tr.stride * sizeof(float);
-    const float stopT = op.stop_T;
-    float Tl = 1.0f, P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
-    march(tr, r, op.max_steps, [&](int leaf, float delta) -> bool {
-        const float s = fmaxf(load_sigma(sig, leaf), 0.0f);
-        if (!(s > 0.0f)) return false;  // no density: zero weight, and dC/dsigma is masked
-        float rec[NL];
-        load_record<float, NL, VEC>(shb + (size_t)leaf * rec_bytes, rec);
-        const float ex = __expf(-(s * delta));
-        const float w = Tl * (1.0f - ex);
-        const float Tn = Tl * ex;
-        const float c0 = sigmoid(dot_channel<K>(rec, Y));
-        const float c1 = sigmoid(dot_channel<K>(rec + K, Y));
-        const float c2 = sigmoid(dot_channel<K>(rec + 2 * K, Y));
-        P0 = fmaf(w, c0, P0);
-        P1 = fmaf(w, c1, P1);
-        P2 = fmaf(w, c2, P2);
-        // dC/dsigma_i = delta_i (c_i T_{i+1} - (C - P_i)), summed over channels
-        float gs = g0 * (c0 * Tn - (C0 - P0));
-        gs = fmaf(g1, c1 * Tn - (C1 - P1), gs);
-        gs = fmaf(g2, c2 * Tn - (C2 - P2), gs);
-        atomicAdd(gsig + leaf, gs * delta);
-        // dC/dk = w c (1 - c) Y
-        float* gk = gsh + (size_t)leaf * tr.stride;
-        const float z0 = g0 * w * c0 * (1.0f - c0);
-        const float z1 = g1 * w * c1 * (1.0f - c1);
-        const float z2 = g2 * w * c2 * (1.0f - c2);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            atomicAdd(gk + k, z0 * Y[k]);
-            atomicAdd(gk + K + k, z1 * Y[k]);
-            atomicAdd(gk + 2 * K + k, z2 * Y[k]);
-        }
-        Tl = Tn;
-        return Tl < stopT;
-    });
+    if (!ray_setup(tr, ro, rd, r)) return;
+    BwdSampler<K, VEC, NL> smp;
+    smp.g0 = grad[3 * i];
+    smp.g1 = grad[3 * i + 1];
+    smp.g2 = grad[3 * i + 2];
+    if (smp.g0 == 0.0f && smp.g1 == 0.0f && smp.g2 == 0.0f) return;
+    smp.C0 = rgb_fwd[3 * i];
+    smp.C1 = rgb_fwd[3 * i + 1];
+    smp.C2 = rgb_fwd[3 * i + 2];
+    smp.sig = static_cast<const float*>(tr.sigma);
+    smp.shb = static_cast<const char*>(tr.sh);
+    smp.rec_bytes = (size_t)tr.stride * sizeof(float);
+    smp.stride = tr.stride;
+    smp.stopT = op.stop_T;
+    smp.gsig = gsig;
+    smp.gsh = gsh;
+    sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], smp.Y);
+    extern __shared__ int po_stack[];
+    march(tr, r, op.max_steps, po_stack + threadIdx.x, smp);
 }
 
 inline int64_t grid_for(int64_t n_blocks) { return 8 * ((n_blocks + 7) / 8); }
+
+// Dynamic LDS of the node stack: one int per lane and tree level.
+inline size_t stack_bytes(int depth) { return sizeof(int) * kBlock * (size_t)depth; }
 
 // Record-load plan: "fast" loads the padded record with the widest vectors,
 // "generic" uses dword loads of exactly the record (rounded to whole dwords).
@@ -471,11 +567,11 @@ hipError_t rays_t(const po_tree* t, int64_t n, const float* o, const float* d, c
     const int64_t nb = (n + kBlock - 1) / kBlock;
     dim3 grid((unsigned)grid_for(nb)), block(kBlock);
     if (use_fast<T, K>(t))
-        hipLaunchKernelGGL((k_render_rays<T, K, P::FAST_VEC, P::FAST_NL>), grid, block, 0, s, t->kt, n, nb, o,
-                           d, op, rgb, aux);
+        hipLaunchKernelGGL((k_render_rays<T, K, P::FAST_VEC, P::FAST_NL>), grid, block, stack_bytes(t->kt.depth),
+                           s, t->kt, n, nb, o, d, op, rgb, aux);
     else
-        hipLaunchKernelGGL((k_render_rays<T, K, 4, P::GEN_NL>), grid, block, 0, s, t->kt, n, nb, o, d, op,
-                           rgb, aux);
+        hipLaunchKernelGGL((k_render_rays<T, K, 4, P::GEN_NL>), grid, block, stack_bytes(t->kt.depth), s, t->kt,
+                           n, nb, o, d, op, rgb, aux);
     return hipGetLastError();
 }
 
@@ -487,11 +583,14 @@ hipError_t camera_t(const po_tree* t, int n_jobs, KJob* jobs, int n_blocks, hipS
     for (int j = n_jobs; j < MAXJ; ++j) B.job[j] = jobs[0];
     B.n_jobs = n_jobs;
     B.n_blocks = n_blocks;
+    int depth = 1;
+    for (int j = 0; j < n_jobs; ++j) depth = max(depth, jobs[j].tr.depth);
     dim3 grid((unsigned)grid_for(n_blocks)), block(kBlock);
     if (use_fast<T, K>(t))
-        hipLaunchKernelGGL((k_render_camera<T, K, P::FAST_VEC, P::FAST_NL, MAXJ>), grid, block, 0, s, B);
+        hipLaunchKernelGGL((k_render_camera<T, K, P::FAST_VEC, P::FAST_NL, MAXJ>), grid, block, stack_bytes(depth),
+                           s, B);
     else
-        hipLaunchKernelGGL((k_render_camera<T, K, 4, P::GEN_NL, MAXJ>), grid, block, 0, s, B);
+        hipLaunchKernelGGL((k_render_camera<T, K, 4, P::GEN_NL, MAXJ>), grid, block, stack_bytes(depth), s, B);
     return hipGetLastError();
 }
 
@@ -502,11 +601,11 @@ hipError_t backward_t(const po_tree* t, int64_t n, const float* o, const float* 
     const int64_t nb = (n + kBlock - 1) / kBlock;
     dim3 grid((unsigned)grid_for(nb)), block(kBlock);
     if (use_fast<float, K>(t))
-        hipLaunchKernelGGL((k_backward<K, P::FAST_VEC, P::FAST_NL>), grid, block, 0, s, t->kt, n, nb, o, d, op,
-                           rgb_fwd, grad, gsig, gsh);
+        hipLaunchKernelGGL((k_backward<K, P::FAST_VEC, P::FAST_NL>), grid, block, stack_bytes(t->kt.depth), s,
+                           t->kt, n, nb, o, d, op, rgb_fwd, grad, gsig, gsh);
     else
-        hipLaunchKernelGGL((k_backward<K, 4, P::GEN_NL>), grid, block, 0, s, t->kt, n, nb, o, d, op, rgb_fwd,
-                           grad, gsig, gsh);
+        hipLaunchKernelGGL((k_backward<K, 4, P::GEN_NL>), grid, block, stack_bytes(t->kt.depth), s, t->kt, n, nb,
+                           o, d, op, rgb_fwd, grad, gsig, gsh);
     return hipGetLastError();
 }
 
