@@ -136,7 +136,7 @@ __device__ __forceinline__ float sigmoid(float z) { return __frcp_rn(1.0f + __ex
 struct Ray {
     double og[3];  // origin, grid units
     double dg[3];  // direction (caller's length), grid units per unit of s
-    double inv[3]; // 1 / dg (0 where dg == 0; never used there)
+    double inv[3]; // 1 / dg
     double len;    // |d| in world units
     float dn[3];   // unit direction, world (SH argument)
     int c[3];      // finest-level coordinates of the current cell
@@ -156,22 +156,22 @@ __device__ __forceinline__ bool ray_setup(const KTree& tr, const double (&o)[3],
     for (int k = 0; k < 3; ++k) {
         r.og[k] = (o[k] - tr.lo[k]) * tr.scale;
         if (!(fabs(r.og[k]) < 1e300)) return false;
-        r.dg[k] = d[k] * tr.scale;
-        if (r.dg[k] == 0.0) {
-            r.inv[k] = 0.0;
-            if (!(r.og[k] >= 0.0 && r.og[k] < N)) return false;  // half-open cell in a grid plane
-        } else {
-            r.inv[k] = 1.0 / r.dg[k];
-            const double ta = (0.0 - r.og[k]) * r.inv[k];
-            const double tb = (N - r.og[k]) * r.inv[k];
-            s0 = fmax(s0, fmin(ta, tb));
-            s1 = fmin(s1, fmax(ta, tb));
-        }
+        // A ray lying in a grid plane (zero component) belongs to the cell
+        // above it (half-open cells): a positive direction component of
+        // 1e-300 grid units gives exactly that, with exit parameters of
+        // ~1e300 that never win, and needs no special case in the walk.
+        const double g = d[k] * tr.scale;
+        r.dg[k] = (g == 0.0) ? 1e-300 : g;
+        r.inv[k] = 1.0 / r.dg[k];
+        const double ta = (0.0 - r.og[k]) * r.inv[k];
+        const double tb = (N - r.og[k]) * r.inv[k];
+        s0 = fmax(s0, fmin(ta, tb));
+        s1 = fmin(s1, fmax(ta, tb));
     }
     if (!(s1 > s0)) return false;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double p = (r.dg[k] == 0.0) ? r.og[k] : fma(s0, r.dg[k], r.og[k]);
+        const double p = fma(s0, r.dg[k], r.og[k]);
         r.c[k] = (int)fmin(fmax(floor(p), 0.0), N - 1.0);
     }
     r.s = s0;
@@ -225,18 +225,16 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
                 leaf = -1;
             }
         }
+        // exit parameter: the nearest far face (branch-free; pos = moving up the axis)
         const int csz = 1 << (D - L);
         int lo[3];
+        bool pos[3];
         double sk[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             lo[k] = r.c[k] & ~(csz - 1);
-            if (r.dg[k] > 0.0)
-                sk[k] = ((double)(lo[k] + csz) - r.og[k]) * r.inv[k];
-            else if (r.dg[k] < 0.0)
-                sk[k] = ((double)lo[k] - r.og[k]) * r.inv[k];
-            else
-                sk[k] = 1e300;
+            pos[k] = r.dg[k] > 0.0;
+            sk[k] = ((double)(lo[k] + (pos[k] ? csz : 0)) - r.og[k]) * r.inv[k];
         }
         const double se = fmax(fmin(fmin(sk[0], sk[1]), sk[2]), r.s);
         ++steps;
@@ -251,22 +249,21 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
                 pending = true;
             }
         }
-        // move across the exit face(s)
+        // move across the exit face(s): axes whose face is reached step to the
+        // neighbouring cell; the others take the finest cell of the exit point,
+        // kept inside the current cube and never moving against the ray
         bool out = false;
         int nc[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            if (sk[k] <= se) {
-                nc[k] = (r.dg[k] > 0.0) ? lo[k] + csz : lo[k] - 1;
-                out |= (nc[k] < 0) | (nc[k] >= N);
-            } else if (r.dg[k] != 0.0) {
-                double p = fma(se, r.dg[k], r.og[k]);
-                p = fmin(fmax(p, (double)lo[k]), (double)(lo[k] + csz - 1));
-                const int q = (int)floor(p);
-                nc[k] = (r.dg[k] > 0.0) ? max(q, r.c[k]) : min(q, r.c[k]);
-            } else {
-                nc[k] = r.c[k];
-            }
+            const int stepped = pos[k] ? lo[k] + csz : lo[k] - 1;
+            double p = fma(se, r.dg[k], r.og[k]);
+            p = fmin(fmax(p, (double)lo[k]), (double)(lo[k] + csz - 1));
+            const int q = (int)floor(p);
+            const int kept = pos[k] ? max(q, r.c[k]) : min(q, r.c[k]);
+            const bool cross = sk[k] <= se;
+            nc[k] = cross ? stepped : kept;
+            out |= cross & ((stepped < 0) | (stepped >= N));
         }
         r.s = se;
         if (out) break;
