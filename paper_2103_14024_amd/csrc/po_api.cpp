@@ -400,7 +400,7 @@ po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_rend
     j.tile_begin = 0;
     j.block_begin = 0;
     j.tiles_x = (cam->width + PO_TILE - 1) / PO_TILE;
-    hipError_t e = po_launch_camera_jobs(t, 1, &j, tiles_of(cam), (hipStream_t)stream);
+    hipError_t e = po_launch_camera_jobs(t, 1, &j, 4 * tiles_of(cam), (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "render_camera launch");
     return ok();
 }
@@ -468,7 +468,7 @@ po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream) {
             k.tile_begin = J.tile_begin;
             k.block_begin = blocks;
             k.tiles_x = (J.cam.width + PO_TILE - 1) / PO_TILE;
-            blocks += nt;
+            blocks += 4 * nt;
         }
         if (nj == 0) continue;
         hipError_t e = po_launch_camera_jobs(jobs[i].tree, nj, kj, blocks, (hipStream_t)stream);

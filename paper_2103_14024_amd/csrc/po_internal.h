@@ -41,7 +41,7 @@ struct KJob {
     float* rgb;
     float* aux;
     int32_t tile_begin;     // first 16x16 tile of the image rendered by this job
-    int32_t block_begin;    // first workgroup (before the XCD swizzle) of this job
+    int32_t block_begin;    // first workgroup (before the XCD swizzle) of this job: 4 per 16x16 tile
     int32_t tiles_x;        // ceil(W / 16)
     int32_t pad_;
 };
@@ -64,7 +64,8 @@ hipError_t po_launch_rays(const po_tree* t, int64_t n, const float* o, const flo
 hipError_t po_launch_backward(const po_tree* t, int64_t n, const float* o, const float* d,
                               const KOpts& op, const float* rgb_fwd, const float* grad_rgb,
                               float* grad_sigma, float* grad_sh, hipStream_t s);
-// Renders camera jobs that all share dtype, K and vec_bytes (at most PO_BATCH_MAX_JOBS).
+// Renders camera jobs that all share dtype, K and vec_bytes (at most
+// PO_BATCH_MAX_JOBS); n_blocks counts workgroups, four per 16x16 tile.
 hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks,
                                  hipStream_t s);
 hipError_t po_read_device_errors(unsigned long long* out);

@@ -29,7 +29,10 @@ __device__ unsigned long long g_po_errors = 0;
 
 namespace {
 
-constexpr int kBlock = 256;  // 4 wave64 per workgroup
+// One wave64 per workgroup: rays finish unevenly, and single-wave workgroups
+// let the dispatcher refill a SIMD as soon as any wave retires, which
+// shortens the tail of a launch.
+constexpr int kBlock = 64;
 
 // ---------------------------------------------------------------------------
 // Real SH basis up to degree 3 at a unit direction (App. B.1), written as
@@ -398,8 +401,8 @@ struct KBatch {
     int32_t n_blocks;
 };
 
-// Camera jobs: one workgroup renders one 16x16 tile; wave w takes the 8x8
-// quadrant (w & 1, w >> 1) and lane l the pixel (l & 7, l >> 3) of it.
+// Camera jobs: a 16x16 tile is rendered by four single-wave workgroups, one
+// per 8x8 quadrant; lane l takes the pixel (l & 7, l >> 3) of its quadrant.
 template <typename T, int K, int VEC, int NL, int MAXJ>
 __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
     const int64_t b = xcd_swizzle(blockIdx.x, B.n_blocks);
@@ -410,11 +413,12 @@ __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
             if (b >= B.job[q].block_begin) j = q;
     }
     const KJob& J = B.job[j];
-    const int tile = J.tile_begin + (int)(b - J.block_begin);
+    const int q = (int)(b - J.block_begin);
+    const int tile = J.tile_begin + (q >> 2), quad = q & 3;
     const int tx = tile % J.tiles_x, ty = tile / J.tiles_x;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int px = tx * 16 + (wave & 1) * 8 + (lane & 7);
-    const int py = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const int lane = threadIdx.x;
+    const int px = tx * 16 + (quad & 1) * 8 + (lane & 7);
+    const int py = ty * 16 + (quad >> 1) * 8 + (lane >> 3);
     if (px >= J.cam.W || py >= J.cam.H) return;
     // pixel-centre ray, evaluated in FP64 like the rest of the ray geometry
     const double x = ((double)px + 0.5 - (double)J.cam.cx) / (double)J.cam.fx;
