@@ -116,6 +116,72 @@ def cpu_baseline(scene, poses, budget_s=12.0):
                       f"rendering, {rays_per_s / 1e6:.2f} Mrays/s)"}
 
 
+def train_leg(po, scenes, steps=100, warmup=5, fit_steps=300, lr=1e7, batch=65536):
+    """Differentiation workload: depth-8 blob tree (SH degree 2, float32),
+    targets = 100 renders of 400x400 from the ground-truth tree, training
+    from a copy perturbed by N(0, 0.3^2), SGD on random batches of 65536
+    rays.  Times full optimisation steps (forward, loss gradient, backward
+    with atomics, SGD) with HIP events and reports the dataset PSNR before
+    and after `fit_steps` steps."""
+    import torch
+
+    gt = scenes.scene_train()
+    tgt = po.Tree.from_scene(gt)
+    fx, fy, cx, cy = scenes.intrinsics(400, 400, 40.0)
+    cams = [po.Camera(p, 400, 400, fx, fy, cx, cy) for p in scenes.hemisphere_poses(100, 4.0, 5)]
+    o, d, t = po.optim.training_set(tgt, cams)
+    del tgt
+    sig, sh = scenes.perturb(gt["sigma"], gt["sh"], 0.3, 7)
+    tree = po.Tree.from_cells(gt["depth"], gt["sh_degree"], gt["cells"], sig, sh)
+    m0 = po.optim.dataset_mse(tree, o, d, t)
+    tr = po.Trainer(tree, o, d, t, lr_sigma=lr, lr_sh=lr, batch=batch, seed=1)
+    for _ in range(warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        tr.step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    for _ in range(max(0, fit_steps - steps - warmup)):
+        tr.step()
+    m1 = po.optim.dataset_mse(tree, o, d, t)
+    return {"workload": "depth-8 blob band (%d leaves), SH degree 2, fp32, 100x400x400 targets, batch %d, "
+                        "SGD lr %g" % (len(gt["cells"]), batch, lr),
+            "ms_per_step": round(ms, 4), "mrays_per_s": round(batch / ms / 1e3, 2),
+            "psnr_start": round(po.psnr(m0), 2), "psnr_after": round(po.psnr(m1), 2), "steps_fitted": fit_steps,
+            "paper_context": "about 3M rays/s on a Tesla V100 (NeRF-synthetic)"}
+
+
+def serve_leg(po, scenes, rates=(50, 100, 200, 350, 500), n_requests=300, budget_mb=1024):
+    """Serving workload: four float16 scenes resident in HBM (depth 8/9/9/10,
+    SH degree 2/3/2/3), Poisson arrivals at each rate, resolutions uniform
+    over 256^2, 512^2, 800^2, 1280x720 and 1920x1080, random upper-hemisphere
+    poses, outputs admitted against an HBM budget.  Reports p50/p99 latency
+    (arrival to completion on the GPU clock) and throughput per rate."""
+    from paper_2103_14024_amd import server
+
+    t0 = time.perf_counter()
+    sc = scenes.serve_scenes()
+    trees = [po.Tree.from_scene(s, dtype="f16") for s in sc]
+    log(f"serve: scenes {[len(s['cells']) for s in sc]} leaves in {time.perf_counter() - t0:.1f} s")
+    srv = server.Server(trees, budget_bytes=budget_mb << 20, max_active=64, chunk_tiles=256, launch_tiles=2048,
+                        streams=3, max_inflight=4)
+    # warm up every kernel variant
+    srv.run(server.poisson_requests(20, 1000.0, len(trees), seed=99))
+    per_rate = {}
+    for k, rate in enumerate(rates):
+        st = srv.run(server.poisson_requests(n_requests, float(rate), len(trees), seed=100 + k))
+        per_rate[str(rate)] = st.summary()
+        log(f"serve {rate} req/s: {per_rate[str(rate)]}")
+    return {"workload": "4 resident fp16 scenes (leaves %s), Poisson arrivals, mixed resolutions, "
+                        "%d requests per rate, %d MB output budget" % ([len(s["cells"]) for s in sc], n_requests,
+                                                                      budget_mb),
+            "by_rate": per_rate}
+
+
 def calib_copy(mib: int):
     """One plain device-to-device copy of `mib` MiB, for scaling the HBM
     traffic counters (it reads and writes exactly that many bytes)."""
@@ -138,6 +204,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=300, help="requests per arrival rate")
     ap.add_argument("--profile", action="store_true",
                     help="time the float32 renders only (no sample-count pass, fp16 or CPU legs); no JSON line")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -203,6 +272,13 @@ def main():
                        "msamples_per_s": round(r16["msamples_per_s"], 1),
                        "alg_gbps": round(r16["alg_gbps"], 1), "speedup_vs_fp32": round(r16["fps"] / r32["fps"], 3)}
         del tree16
+    if not args.no_train:
+        log("differentiation: direct octree optimisation")
+        out["train"] = train_leg(po, scenes)
+        log(f"train: {out['train']['mrays_per_s']} Mrays/s, PSNR {out['train']['psnr_start']} -> "
+            f"{out['train']['psnr_after']}")
+    if not args.no_serve:
+        out["serve"] = serve_leg(po, scenes, n_requests=args.serve_requests)
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)")
         out["cpu_baseline"] = cpu_baseline(scene, poses)

@@ -165,6 +165,14 @@ po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, co
 po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_render_opts* opts,
                            float* d_rgb, float* d_aux, void* stream);
 
+/* po_camera_rays: writes the pixel-centre rays of a camera, in row-major
+ * pixel order, as d_origins[H*W][3] (the camera position) and
+ * d_dirs[H*W][3] (unit directions, evaluated in FP64 and rounded to float32).
+ * Rendering these rays with po_render_rays gives the camera image up to the
+ * float32 rounding of the directions.  Used to build ray batches for the
+ * optimisation of Sec. 4.3.  Errors: PO_ERR_INVALID, PO_ERR_DEVICE. */
+po_status po_camera_rays(const po_camera* cam, float* d_origins, float* d_dirs, void* stream);
+
 /* -------------------------------------------------------------- gradients
  * Accumulates (+=) into d_grad_sigma[n_leaves] and d_grad_sh[n_leaves][sh_stride]
  * the gradient of L with respect to the raw leaf values, given
@@ -182,6 +190,23 @@ po_status po_render_rays_backward(const po_tree* t, int64_t n, const float* d_or
                                   const float* d_dirs, const po_render_opts* opts,
                                   const float* d_rgb_fwd, const float* d_grad_rgb,
                                   float* d_grad_sigma, float* d_grad_sh, void* stream);
+
+/* ------------------------------------------------------------ optimisation
+ * Direct optimisation of the leaf values (Sec. 4.3; App. B.5): the NeRF
+ * loss of Sec. 3 (eqn:nerfloss), reduced here as a mean over the batch and
+ * the colour channels, minimised by plain SGD with the tree structure fixed.
+ *
+ * po_mse_grad: for n rays, d_grad_rgb[i][c] = scale * 2 (rgb - target) and
+ * d_sq_sum[0] += sum of (rgb - target)^2 (one float; the caller zeroes it;
+ * float atomics, so the last bits of the sum depend on scheduling).  scale =
+ * 1 / (3 n) gives the gradient of the mean.  Errors: PO_ERR_INVALID,
+ * PO_ERR_DEVICE.
+ * po_sgd_step: d_param[i] -= lr * d_grad[i] for i < n and, if zero_grad is
+ * non-zero, d_grad[i] = 0 in the same pass.  Errors: PO_ERR_INVALID
+ * (NULL arrays with n > 0, n < 0, non-finite lr), PO_ERR_DEVICE. */
+po_status po_mse_grad(int64_t n, const float* d_rgb, const float* d_target, float scale, float* d_grad_rgb,
+                      float* d_sq_sum, void* stream);
+po_status po_sgd_step(int64_t n, float* d_param, float* d_grad, float lr, int32_t zero_grad, void* stream);
 
 /* ---------------------------------------------------------------- batches
  * One job renders the 16x16 tiles [tile_begin, tile_end) of one camera

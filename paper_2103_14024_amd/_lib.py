@@ -67,6 +67,9 @@ _SIGS = {
     "po_render_rays_backward": [_P, _I64, _P, _P, ctypes.POINTER(po_render_opts), _P, _P, _P, _P, _P],
     "po_render_batch": [_I32, ctypes.POINTER(po_job), _P],
     "po_camera_tiles": [ctypes.POINTER(po_camera), ctypes.POINTER(_I32)],
+    "po_camera_rays": [ctypes.POINTER(po_camera), _P, _P, _P],
+    "po_mse_grad": [_I64, _P, _P, ctypes.c_float, _P, _P, _P],
+    "po_sgd_step": [_I64, _P, _P, ctypes.c_float, _I32, _P],
     "po_device_errors": [ctypes.POINTER(_I64)],
     "po_device_errors_reset": [],
 }

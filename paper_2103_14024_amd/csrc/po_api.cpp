@@ -422,6 +422,35 @@ po_status po_render_rays_backward(const po_tree* t, int64_t n, const float* d_or
     return ok();
 }
 
+po_status po_camera_rays(const po_camera* cam, float* d_origins, float* d_dirs, void* stream) {
+    if (po_status s = check_camera(cam)) return s;
+    if (!d_origins || !d_dirs) return fail(PO_ERR_INVALID, "NULL array");
+    hipError_t e = po_launch_camera_rays(kcam(cam), d_origins, d_dirs, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "camera_rays launch");
+    return ok();
+}
+
+po_status po_mse_grad(int64_t n, const float* d_rgb, const float* d_target, float scale, float* d_grad_rgb,
+                      float* d_sq_sum, void* stream) {
+    if (n < 0 || n > (1ll << 40)) return fail(PO_ERR_INVALID, "n = %lld out of range", (long long)n);
+    if (!finite(scale)) return fail(PO_ERR_INVALID, "scale must be finite");
+    if (n == 0) return ok();
+    if (!d_rgb || !d_target || !d_grad_rgb || !d_sq_sum) return fail(PO_ERR_INVALID, "NULL array");
+    hipError_t e = po_launch_mse_grad(n, d_rgb, d_target, scale, d_grad_rgb, d_sq_sum, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "mse_grad launch");
+    return ok();
+}
+
+po_status po_sgd_step(int64_t n, float* d_param, float* d_grad, float lr, int32_t zero_grad, void* stream) {
+    if (n < 0 || n > (1ll << 40)) return fail(PO_ERR_INVALID, "n = %lld out of range", (long long)n);
+    if (!finite(lr)) return fail(PO_ERR_INVALID, "lr must be finite");
+    if (n == 0) return ok();
+    if (!d_param || !d_grad) return fail(PO_ERR_INVALID, "NULL array");
+    hipError_t e = po_launch_sgd(n, d_param, d_grad, lr, zero_grad != 0, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "sgd launch");
+    return ok();
+}
+
 po_status po_camera_tiles(const po_camera* cam, int32_t* n_tiles) {
     if (po_status s = check_camera(cam)) return s;
     if (!n_tiles) return fail(PO_ERR_INVALID, "n_tiles is NULL");

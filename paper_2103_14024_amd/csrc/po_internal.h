@@ -68,6 +68,10 @@ hipError_t po_launch_backward(const po_tree* t, int64_t n, const float* o, const
 // PO_BATCH_MAX_JOBS); n_blocks counts workgroups, four per 16x16 tile.
 hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks,
                                  hipStream_t s);
+hipError_t po_launch_camera_rays(const KCam& cam, float* o, float* d, hipStream_t s);
+hipError_t po_launch_mse_grad(int64_t n, const float* rgb, const float* target, float scale, float* grad,
+                              float* sq_sum, hipStream_t s);
+hipError_t po_launch_sgd(int64_t n, float* param, float* grad, float lr, bool zero_grad, hipStream_t s);
 hipError_t po_read_device_errors(unsigned long long* out);
 // Kernel variant a tree renders with (dtype, K, record-load plan); jobs of one
 // batched launch must share it.

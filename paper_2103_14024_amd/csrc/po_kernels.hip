@@ -394,6 +394,33 @@ __global__ __launch_bounds__(kBlock) void k_render_rays(KTree tr, int64_t n, int
     }
 }
 
+// Pinhole ray through the centre of pixel (px, py), in FP64 like the rest of
+// the ray geometry (direction not normalised).
+__device__ __forceinline__ void pixel_ray(const KCam& cam, int px, int py, double (&ro)[3], double (&rd)[3]) {
+    const double x = ((double)px + 0.5 - (double)cam.cx) / (double)cam.fx;
+    const double y = -(((double)py + 0.5 - (double)cam.cy) / (double)cam.fy);
+    const float* M = cam.c2w;
+    rd[0] = (double)M[0] * x + (double)M[1] * y - (double)M[2];
+    rd[1] = (double)M[4] * x + (double)M[5] * y - (double)M[6];
+    rd[2] = (double)M[8] * x + (double)M[9] * y - (double)M[10];
+    ro[0] = (double)M[3];
+    ro[1] = (double)M[7];
+    ro[2] = (double)M[11];
+}
+
+__global__ __launch_bounds__(256) void k_camera_rays(KCam cam, float* __restrict__ o, float* __restrict__ d) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (int64_t)cam.W * cam.H) return;
+    double ro[3], rd[3];
+    pixel_ray(cam, (int)(p % cam.W), (int)(p / cam.W), ro, rd);
+    const double il = 1.0 / sqrt(rd[0] * rd[0] + rd[1] * rd[1] + rd[2] * rd[2]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        o[3 * p + k] = (float)ro[k];
+        d[3 * p + k] = (float)(rd[k] * il);
+    }
+}
+
 template <int MAXJ>
 struct KBatch {
     KJob job[MAXJ];
@@ -420,14 +447,8 @@ __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
     const int px = tx * 16 + (quad & 1) * 8 + (lane & 7);
     const int py = ty * 16 + (quad >> 1) * 8 + (lane >> 3);
     if (px >= J.cam.W || py >= J.cam.H) return;
-    // pixel-centre ray, evaluated in FP64 like the rest of the ray geometry
-    const double x = ((double)px + 0.5 - (double)J.cam.cx) / (double)J.cam.fx;
-    const double y = -(((double)py + 0.5 - (double)J.cam.cy) / (double)J.cam.fy);
-    const float* M = J.cam.c2w;
-    const double rd[3] = {(double)M[0] * x + (double)M[1] * y - (double)M[2],
-                          (double)M[4] * x + (double)M[5] * y - (double)M[6],
-                          (double)M[8] * x + (double)M[9] * y - (double)M[10]};
-    const double ro[3] = {(double)M[3], (double)M[7], (double)M[11]};
+    double ro[3], rd[3];
+    pixel_ray(J.cam, px, py, ro, rd);
     float C[3], Tr;
     int ns, steps;
     extern __shared__ int po_stack[];
@@ -539,6 +560,36 @@ __global__ __launch_bounds__(kBlock) void k_backward(KTree tr, int64_t n, int64_
     march(tr, r, op.max_steps, po_stack + threadIdx.x, smp);
 }
 
+// Loss gradient of the NeRF loss (Sec. 3, eqn:nerfloss) for one batch: one
+// thread per ray; squared errors are summed within the wave and added once
+// per wave.
+__global__ __launch_bounds__(256) void k_mse_grad(int64_t n, const float* __restrict__ rgb,
+                                                  const float* __restrict__ target, float scale,
+                                                  float* __restrict__ grad, float* __restrict__ sq_sum) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float e2 = 0.0f;
+    if (i < n) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float e = rgb[3 * i + c] - target[3 * i + c];
+            grad[3 * i + c] = scale * (2.0f * e);
+            e2 = fmaf(e, e, e2);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) e2 += __shfl_xor(e2, off, 64);
+    if ((threadIdx.x & 63) == 0 && e2 != 0.0f) atomicAdd(sq_sum, e2);
+}
+
+// Plain SGD on the leaf values (Sec. 4.3): p -= lr g, optionally clearing g.
+__global__ __launch_bounds__(256) void k_sgd(int64_t n, float* __restrict__ p, float* __restrict__ g, float lr,
+                                             int zero_grad) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    p[i] = fmaf(-lr, gi, p[i]);
+    if (zero_grad) g[i] = 0.0f;
+}
+
 inline int64_t grid_for(int64_t n_blocks) { return 8 * ((n_blocks + 7) / 8); }
 
 // Dynamic LDS of the node stack: one int per lane and tree level.
@@ -648,6 +699,25 @@ hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, i
 hipError_t po_launch_backward(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
                               const float* rgb_fwd, const float* grad, float* gsig, float* gsh, hipStream_t s) {
     PO_DISPATCH_K(t->K, (backward_t<KK>(t, n, o, d, op, rgb_fwd, grad, gsig, gsh, s)));
+}
+
+hipError_t po_launch_camera_rays(const KCam& cam, float* o, float* d, hipStream_t s) {
+    const int64_t n = (int64_t)cam.W * cam.H;
+    hipLaunchKernelGGL(k_camera_rays, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cam, o, d);
+    return hipGetLastError();
+}
+
+hipError_t po_launch_mse_grad(int64_t n, const float* rgb, const float* target, float scale, float* grad,
+                              float* sq_sum, hipStream_t s) {
+    hipLaunchKernelGGL(k_mse_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, rgb, target, scale, grad,
+                       sq_sum);
+    return hipGetLastError();
+}
+
+hipError_t po_launch_sgd(int64_t n, float* param, float* grad, float lr, bool zero_grad, hipStream_t s) {
+    hipLaunchKernelGGL(k_sgd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, param, grad, lr,
+                       zero_grad ? 1 : 0);
+    return hipGetLastError();
 }
 
 hipError_t po_read_device_errors(unsigned long long* out) {

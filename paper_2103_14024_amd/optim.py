@@ -1,0 +1,107 @@
+"""Direct optimisation of a PlenOctree's leaf values (Sec. 4.3; App. B.5).
+
+The tree structure is fixed; the raw densities and SH coefficients of a
+float32 tree are fitted to target pixel colours with the NeRF loss (Sec. 3,
+eqn:nerfloss; here the mean over the batch and the colour channels) and plain
+SGD.  One step: forward render of a random ray batch (the first pass of the
+App. B.3 scheme), loss gradient, backward replay with atomics (second pass),
+SGD update that also clears the gradients -- four library kernels.  torch
+only holds the buffers and draws the batch indices.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib as L
+from .render import _stream_ptr, make_opts
+
+
+class Trainer:
+    """SGD on tree.sigma and tree.sh (float32 tree) against a ray dataset.
+
+    origins, dirs, target: (N, 3) float32 device tensors (all training
+    pixels); each step draws `batch` of them uniformly with replacement."""
+
+    def __init__(self, tree, origins, dirs, target, lr_sigma, lr_sh, batch=65536, bg=(1.0, 1.0, 1.0), stop_T=1e-4,
+                 seed=0):
+        import torch
+
+        if tree.dtype != L.PO_F32:
+            raise ValueError("optimisation needs a float32 tree")
+        self.tree, self.o, self.d, self.t = tree, origins, dirs, target
+        self.lr_sigma, self.lr_sh, self.batch = float(lr_sigma), float(lr_sh), int(batch)
+        self.bg, self.stop_T = tuple(bg), float(stop_T)
+        dev = origins.device
+        self.gen = torch.Generator(device=dev)
+        self.gen.manual_seed(seed)
+        f = dict(dtype=torch.float32, device=dev)
+        self.bo = torch.empty((batch, 3), **f)
+        self.bd = torch.empty((batch, 3), **f)
+        self.bt = torch.empty((batch, 3), **f)
+        self.rgb = torch.empty((batch, 3), **f)
+        self.grad_rgb = torch.empty((batch, 3), **f)
+        self.sq = torch.zeros(1, **f)
+        self.g_sigma = torch.zeros_like(tree.sigma)
+        self.g_sh = torch.zeros_like(tree.sh)
+        self.opts = make_opts(bg, stop_T)
+        self.steps = 0
+
+    def step(self, stream=None):
+        """One SGD step; returns the batch loss as a 1-element device tensor
+        (mean squared error over rays and channels)."""
+        import torch
+
+        s = _stream_ptr(stream)
+        n = self.batch
+        idx = torch.randint(0, self.o.shape[0], (n,), device=self.o.device, generator=self.gen)
+        torch.index_select(self.o, 0, idx, out=self.bo)
+        torch.index_select(self.d, 0, idx, out=self.bd)
+        torch.index_select(self.t, 0, idx, out=self.bt)
+        self.sq.zero_()
+        tr = self.tree
+        L.call("po_render_rays", tr.handle, n, self.bo.data_ptr(), self.bd.data_ptr(), ctypes.byref(self.opts),
+               self.rgb.data_ptr(), None, s)
+        L.call("po_mse_grad", n, self.rgb.data_ptr(), self.bt.data_ptr(), ctypes.c_float(1.0 / (3 * n)),
+               self.grad_rgb.data_ptr(), self.sq.data_ptr(), s)
+        L.call("po_render_rays_backward", tr.handle, n, self.bo.data_ptr(), self.bd.data_ptr(),
+               ctypes.byref(self.opts), self.rgb.data_ptr(), self.grad_rgb.data_ptr(), self.g_sigma.data_ptr(),
+               self.g_sh.data_ptr(), s)
+        L.call("po_sgd_step", tr.sigma.numel(), tr.sigma.data_ptr(), self.g_sigma.data_ptr(),
+               ctypes.c_float(self.lr_sigma), 1, s)
+        L.call("po_sgd_step", tr.sh.numel(), tr.sh.data_ptr(), self.g_sh.data_ptr(), ctypes.c_float(self.lr_sh), 1,
+               s)
+        self.steps += 1
+        return self.sq / (3 * n)
+
+
+def training_set(gt_tree, cams, bg=(1.0, 1.0, 1.0), stop_T=1e-4, device="cuda"):
+    """Rays of all pixels of `cams` and their colours rendered from gt_tree:
+    (origins, dirs, target), each (sum H*W, 3) float32 on `device`."""
+    import torch
+
+    from .render import camera_rays, render_rays
+
+    os_, ds_, ts_ = [], [], []
+    for cam in cams:
+        o, d = camera_rays(cam, device=device)
+        os_.append(o)
+        ds_.append(d)
+        ts_.append(render_rays(gt_tree, o, d, bg=bg, stop_T=stop_T))
+    return torch.cat(os_), torch.cat(ds_), torch.cat(ts_)
+
+
+def dataset_mse(tree, origins, dirs, target, bg=(1.0, 1.0, 1.0), stop_T=1e-4, chunk=1 << 20) -> float:
+    """Mean squared error of the tree's renders over a whole ray set."""
+    from .render import render_rays
+
+    tot = 0.0
+    for a in range(0, origins.shape[0], chunk):
+        rgb = render_rays(tree, origins[a:a + chunk], dirs[a:a + chunk], bg=bg, stop_T=stop_T)
+        tot += float(((rgb - target[a:a + chunk]) ** 2).sum())
+    return tot / (3 * origins.shape[0])
+
+
+def psnr(mse: float) -> float:
+    import math
+
+    return -10.0 * math.log10(max(mse, 1e-30))

@@ -98,6 +98,17 @@ def render_camera(tree, cam: Camera, bg=(1.0, 1.0, 1.0), stop_T=1e-4, aux=False,
     return (img, a) if aux else img
 
 
+def camera_rays(cam: Camera, stream=None, device="cuda"):
+    """(origins, unit dirs) of a camera's pixel-centre rays, (H*W, 3) float32 each."""
+    torch = _torch()
+    n = cam.width * cam.height
+    o = torch.empty((n, 3), dtype=torch.float32, device=device)
+    d = torch.empty((n, 3), dtype=torch.float32, device=device)
+    c = cam.to_c()
+    L.call("po_camera_rays", ctypes.byref(c), o.data_ptr(), d.data_ptr(), _stream_ptr(stream))
+    return o, d
+
+
 def render_rays_backward(tree, origins, dirs, rgb_fwd, grad_rgb, bg=(1.0, 1.0, 1.0), stop_T=1e-4, max_steps=0,
                          grad_sigma=None, grad_sh=None, stream=None):
     """Accumulates dL/dsigma (n_leaves,) and dL/dsh (n_leaves, stride); returns both."""

@@ -311,6 +311,21 @@ def scene_blobs(depth: int = 9, sh_degree: int = 3, seed: int = 0, data_seed: in
                 cells=cells, sigma=sigma, sh=sh)
 
 
+def scene_train(depth: int = 8, sh_degree: int = 2, seed: int = 1, data_seed: int = 3):
+    """Ground-truth tree of the differentiation workload: the blob band at
+    depth 8 (~0.64M leaves) with its own seeds, SH degree 2."""
+    return scene_blobs(depth, sh_degree, seed, data_seed)
+
+
+# (depth, SH degree, geometry seed) of the four resident scenes of the serving workload
+SERVE_SCENES = [(8, 2, 11), (9, 3, 0), (9, 2, 12), (10, 3, 13)]
+
+
+def serve_scenes(data_seed: int = 21):
+    """The four resident scenes of the serving workload (0.6M to 9.5M leaves)."""
+    return [scene_blobs(d, l, s, data_seed + i) for i, (d, l, s) in enumerate(SERVE_SCENES)]
+
+
 def small_pose(seed: int = 2, radius: float = 4.0) -> np.ndarray:
     """One camera on the upper hemisphere of the radius-4 sphere."""
     return hemisphere_poses(1, radius, seed)[0]

@@ -1,0 +1,42 @@
+"""The render server: every image produced in the batched, continuously
+admitted mix equals the same request rendered alone (bit-identical), and
+admission never exceeds the output-memory budget or the slot cap."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2103_14024_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def po():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_2103_14024_amd as po
+
+    return po
+
+
+def test_alone_equals_mix(po):
+    from paper_2103_14024_amd import server
+
+    sc = [scenes.scene_small(), scenes.scene_blobs(depth=6, sh_degree=3, seed=2, data_seed=3),
+          scenes.scene_blobs(depth=7, sh_degree=2, seed=4, data_seed=5)]
+    trees = [po.Tree.from_scene(sc[0], dtype="f16"), po.Tree.from_scene(sc[1], dtype="f16"),
+             po.Tree.from_scene(sc[2], dtype="f32")]
+    reqs = server.poisson_requests(60, 400.0, 3, seed=9)
+    budget = 40 << 20   # forces queueing behind the memory budget (a 1080p image takes 24.9 MB)
+    srv = server.Server(trees, budget_bytes=budget, max_active=6, chunk_tiles=64, launch_tiles=512, streams=3)
+    st = srv.run(reqs, keep_images=True)
+    s = st.summary()
+    print(f"[gpu] server: {s}", file=sys.stderr, flush=True)
+    assert s["requests"] == 60 and st.max_active <= 6 and st.max_bytes <= budget
+    assert s["jobs_per_launch"] > 1.0
+    for r in reqs:
+        alone = po.render_camera(trees[r.scene], r.cam).cpu().numpy()
+        assert np.array_equal(alone, r.image), r.rid
+        assert r.t_done >= r.arrival
