@@ -181,6 +181,13 @@ __device__ __forceinline__ bool ray_setup(const KTree& tr, const double (&o)[3],
     return true;
 }
 
+// Buffer resource for raw (byte-addressed) loads from one array: loads at
+// offsets outside [0, bytes) return 0 instead of faulting (gfx9 descriptor
+// word 3 = 0x00020000: raw buffer, 32-bit data format).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
 // Walks the segments of a ray.  Data leaves crossed over a positive length
 // go through a two-stage sampler: smp.issue(leaf, delta) starts the loads of
 // the leaf's density and SH record, and smp.consume() -- called one step
@@ -200,33 +207,33 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
                                      Sampler& smp) {
     const int D = tr.depth;
     const int N = 1 << D;
+    // the child array through a buffer descriptor: an entry beyond the array
+    // reads as 0 (empty), so a malformed node index cannot fault
+    const __amdgpu_buffer_rsrc_t child = raw_rsrc(tr.child, (uint32_t)tr.n_nodes * 32u);
     int steps = 0;
     int node = 0, L = 0;
-    bool pending = false;
+    bool pending = false, bad = false;
     while (true) {
-        // descend from (node, level L) to the leaf (data or empty) holding cell c
+        // descend from (node, level L) to the leaf (data or empty) holding cell c;
+        // an internal entry below depth D or beyond the array is malformed and
+        // taken as empty
         int e;
         while (true) {
             stk[L * kBlock] = node;
             const int sft = D - 1 - L;
             const int oct = (((r.c[0] >> sft) & 1) << 2) | (((r.c[1] >> sft) & 1) << 1) | ((r.c[2] >> sft) & 1);
-            e = __ldg(tr.child + ((size_t)node * 8 + oct));
+            e = __builtin_amdgcn_raw_buffer_load_b32(child, ((uint32_t)node << 5) | ((uint32_t)oct << 2), 0, 0);
             ++L;
+            const bool malformed = (e > 0) & ((L >= D) | (e >= tr.n_nodes));
+            bad |= malformed;
+            e = malformed ? 0 : e;
             if (e <= 0) break;
-            if (L >= D || e >= tr.n_nodes) {  // malformed: treat as empty
-                atomicAdd(&g_po_errors, 1ull);
-                e = 0;
-                break;
-            }
             node = e;
         }
-        int leaf = -1;
-        if (e < 0) {
-            leaf = -1 - e;
-            if (leaf >= tr.n_leaves) {
-                atomicAdd(&g_po_errors, 1ull);
-                leaf = -1;
-            }
+        int leaf = -1 - e;
+        if (leaf >= tr.n_leaves) {
+            bad = true;
+            leaf = -1;
         }
         // exit parameter: the nearest far face (branch-free; pos = moving up the axis)
         const int csz = 1 << (D - L);
@@ -243,7 +250,7 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
         ++steps;
         if (pending) {
             pending = false;
-            if (smp.consume()) return steps;
+            if (smp.consume()) break;
         }
         if (leaf >= 0) {
             const float delta = (float)((se - r.s) * r.len);
@@ -255,14 +262,13 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
         // move across the exit face(s): axes whose face is reached step to the
         // neighbouring cell; the others take the finest cell of the exit point,
         // kept inside the current cube and never moving against the ray
+        // (truncation equals floor here: the result is clamped to >= lo >= 0)
         bool out = false;
         int nc[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int stepped = pos[k] ? lo[k] + csz : lo[k] - 1;
-            double p = fma(se, r.dg[k], r.og[k]);
-            p = fmin(fmax(p, (double)lo[k]), (double)(lo[k] + csz - 1));
-            const int q = (int)floor(p);
+            const int q = min(max((int)fma(se, r.dg[k], r.og[k]), lo[k]), lo[k] + csz - 1);
             const int kept = pos[k] ? max(q, r.c[k]) : min(q, r.c[k]);
             const bool cross = sk[k] <= se;
             nc[k] = cross ? stepped : kept;
@@ -271,7 +277,7 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
         r.s = se;
         if (out) break;
         if (steps >= max_steps) {
-            atomicAdd(&g_po_errors, 1ull);
+            bad = true;
             break;
         }
         // deepest common ancestor: the cells agree on the coordinate bits above
@@ -284,6 +290,8 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
         r.c[2] = nc[2];
     }
     if (pending) smp.consume();
+    // a lane that met a malformed entry or the step cap is counted once
+    if (bad) atomicAdd(&g_po_errors, 1ull);
     return steps;
 }
 
