@@ -144,7 +144,9 @@ po_status po_tree_validate(const po_tree_desc* desc, int64_t n_nodes, const int3
  * entry, or an internal node below depth D, as empty space and count it in
  * the device error counter (po_device_errors), so a malformed array cannot
  * make them read out of bounds.  d_sh must be aligned to 4 bytes (16 for the
- * fastest loads).  Errors: PO_ERR_INVALID. */
+ * fastest loads).  Each of the three arrays must be smaller than 4 GiB - 256
+ * bytes (the kernels address them with 32-bit buffer offsets); larger trees
+ * return PO_ERR_UNSUPPORTED.  Errors: PO_ERR_INVALID, PO_ERR_UNSUPPORTED. */
 po_status po_tree_bind(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child,
                        int64_t n_leaves, const void* d_sigma, const void* d_sh, po_tree** out);
 po_status po_tree_destroy(po_tree* t);

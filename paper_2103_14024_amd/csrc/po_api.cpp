@@ -331,6 +331,15 @@ po_status po_tree_bind(const po_tree_desc* desc, int64_t n_nodes, const int32_t*
     const int es = elem_size(desc->dtype);
     if (((uintptr_t)d_child) % 4 || ((uintptr_t)d_sigma) % es || ((uintptr_t)d_sh) % 4)
         return fail(PO_ERR_INVALID, "misaligned device array");
+    {
+        // the kernels address each array through a 32-bit buffer offset
+        const int K = (desc->sh_degree + 1) * (desc->sh_degree + 1);
+        const int64_t stride = desc->sh_stride ? desc->sh_stride : 3 * K;
+        const uint64_t lim = (1ull << 32) - 256;
+        if ((uint64_t)n_nodes * 32u >= lim || (uint64_t)n_leaves * es >= lim ||
+            (uint64_t)n_leaves * (uint64_t)stride * es >= lim)
+            return fail(PO_ERR_UNSUPPORTED, "a tree array exceeds 4 GiB");
+    }
     po_tree* t = new (std::nothrow) po_tree();
     if (!t) return fail(PO_ERR_OOM, "tree handle allocation");
     t->desc = *desc;
@@ -357,6 +366,8 @@ po_status po_tree_bind(const po_tree_desc* desc, int64_t n_nodes, const int32_t*
     k.n_leaves = (int32_t)n_leaves;
     k.stride = t->stride;
     k.depth = desc->depth;
+    k.sigma_bytes = (uint32_t)(n_leaves * es);
+    k.sh_bytes = (uint32_t)(n_leaves * (int64_t)t->stride * es);
     for (int a = 0; a < 3; ++a) k.lo[a] = (double)desc->center[a] - (double)desc->half_size;
     k.scale = (double)(1 << desc->depth) / (2.0 * (double)desc->half_size);
     *out = t;

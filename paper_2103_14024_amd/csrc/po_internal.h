@@ -16,6 +16,8 @@ struct KTree {
     int32_t n_leaves;
     int32_t stride;         // elements per SH record
     int32_t depth;          // D
+    uint32_t sigma_bytes;   // n_leaves * element size (< 2^32)
+    uint32_t sh_bytes;      // n_leaves * stride * element size (< 2^32 - 256)
     double lo[3];           // box minimum corner, world units
     double scale;           // grid units (finest cells) per world unit: 2^D / (2 half)
 };

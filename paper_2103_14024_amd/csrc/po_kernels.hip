@@ -67,6 +67,13 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float (&Y)[K
     }
 }
 
+// Buffer resource for raw (byte-addressed) loads from one array: loads at
+// offsets outside [0, bytes) return 0 instead of faulting (gfx9 descriptor
+// word 3 = 0x00020000: raw buffer, 32-bit data format).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
 // ---------------------------------------------------------------------------
 // Leaf record access.  T is float or __half; values are widened to float.
 // ---------------------------------------------------------------------------
@@ -112,6 +119,44 @@ __device__ __forceinline__ void load_words(const char* __restrict__ base, uint32
     if constexpr (NB % 4 != 0) w[FULLW] = *reinterpret_cast<const uint16_t*>(base + 4 * FULLW);
 }
 
+// Same as load_words, through a raw buffer descriptor at byte offset `off`.
+// An offset at or beyond the end of the buffer returns zeros and touches no
+// memory, which lets lanes without a sample run the same straight-line code.
+template <typename T, int NL, int VEC>
+__device__ __forceinline__ void load_words_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off,
+                                               uint32_t (&w)[Words<T, NL>::N]) {
+    constexpr int NB = Words<T, NL>::NB;
+    constexpr int NV = NB / VEC;
+    constexpr int DONE = NV * VEC / 4;
+    constexpr int FULLW = NB / 4;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if constexpr (VEC == 16) {
+            const auto q = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16 * v, 0, 0);
+            w[4 * v + 0] = q[0];
+            w[4 * v + 1] = q[1];
+            w[4 * v + 2] = q[2];
+            w[4 * v + 3] = q[3];
+        } else if constexpr (VEC == 8) {
+            const auto q = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 8 * v, 0, 0);
+            w[2 * v + 0] = q[0];
+            w[2 * v + 1] = q[1];
+        } else {
+            w[v] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * v, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = DONE; i < FULLW; ++i) w[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * i, 0, 0);
+    if constexpr (NB % 4 != 0) w[FULLW] = __builtin_amdgcn_raw_buffer_load_b16(rs, off + 4 * FULLW, 0, 0);
+}
+
+__device__ __forceinline__ float sigma_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off, float*) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+}
+__device__ __forceinline__ float sigma_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off, __half*) {
+    return __half2float(__ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0)));
+}
+
 // Element i of a record held as raw words, widened to float.
 template <typename T, int NW>
 __device__ __forceinline__ float word_elem(const uint32_t (&w)[NW], int i) {
@@ -123,7 +168,9 @@ __device__ __forceinline__ float word_elem(const uint32_t (&w)[NW], int i) {
     }
 }
 
-__device__ __forceinline__ float sigmoid(float z) { return __frcp_rn(1.0f + __expf(-z)); }
+// Logistic sigmoid (Sec. 4.1) with the hardware reciprocal (1 ulp): the
+// correctly rounded division costs ~10 instructions per colour channel.
+__device__ __forceinline__ float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 // ---------------------------------------------------------------------------
 // Ray geometry in grid units: the box spans [0, 2^D]^3 and finest cells have
@@ -181,54 +228,68 @@ __device__ __forceinline__ bool ray_setup(const KTree& tr, const double (&o)[3],
     return true;
 }
 
-// Buffer resource for raw (byte-addressed) loads from one array: loads at
-// offsets outside [0, bytes) return 0 instead of faulting (gfx9 descriptor
-// word 3 = 0x00020000: raw buffer, 32-bit data format).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+// Child slot of cell c below a node of level L (bits D-1-L of the coordinates).
+__device__ __forceinline__ uint32_t child_slot(const int (&c)[3], int D, int L) {
+    const int sft = D - 1 - L;
+    return (uint32_t)((((c[0] >> sft) & 1) << 2) | (((c[1] >> sft) & 1) << 1) | ((c[2] >> sft) & 1));
 }
 
 // Walks the segments of a ray.  Data leaves crossed over a positive length
 // go through a two-stage sampler: smp.issue(leaf, delta) starts the loads of
-// the leaf's density and SH record, and smp.consume() -- called one step
-// later, after the next cell's descent -- shades and composites it and
-// returns true to stop the walk.  The gather of one sample thus overlaps the
-// tree loads of the next step.  The samples, their order and the stop point
-// are those of the plain front-to-back walk.  Returns the number of cells
-// visited.
+// the leaf's density and SH record (leaf -1: a lane without a sample, which
+// loads nothing), and smp.consume() shades and composites the sample one step
+// later and returns true to stop the walk.  The samples, their order and the
+// stop point are those of the plain front-to-back walk.  Returns the number
+// of cells visited.
 //
-// stk is this lane's column of a [level][kBlock] node stack in LDS: the
-// descent records the node it passes at every level, and after a step the
-// next descent restarts from the deepest ancestor shared by the old and the
-// new cell (the level of the highest differing coordinate bit) instead of
-// the root, so a step costs one or two dependent loads instead of ~D.
+// Per step: finish the descent to the leaf holding cell c; compute the exit
+// parameter and the next cell; prefetch the next cell's first child entry;
+// composite the previous sample; start this cell's gather.  Loads complete in
+// issue order, so the next descent waits only for its own entry and not for
+// the gather, and compositing runs while that entry is in flight.
+//
+// stk is this lane's column of a [level][kBlock] node stack in LDS holding
+// the node of every level on the path to c.  The next descent restarts from
+// the deepest ancestor shared by the old and the new cell (the level of the
+// highest differing coordinate bit) instead of the root, so a step costs one
+// or two dependent loads instead of ~D.  The child array is read through a
+// buffer descriptor: an entry beyond the array reads as 0 (empty), and an
+// internal entry below depth D or past the node count is counted as
+// malformed and taken as empty.
 template <class Sampler>
 __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int* __restrict__ stk,
                                      Sampler& smp) {
     const int D = tr.depth;
     const int N = 1 << D;
-    // the child array through a buffer descriptor: an entry beyond the array
-    // reads as 0 (empty), so a malformed node index cannot fault
-    const __amdgpu_buffer_rsrc_t child = raw_rsrc(tr.child, (uint32_t)tr.n_nodes * 32u);
+    const uint32_t tr_child_end = (uint32_t)tr.n_nodes * 32u;
+    const __amdgpu_buffer_rsrc_t child = raw_rsrc(tr.child, tr_child_end);
     int steps = 0;
-    int node = 0, L = 0;
     bool pending = false, bad = false;
+    int L = 0, node = 0;
+    stk[0] = 0;
+    int e = __builtin_amdgcn_raw_buffer_load_b32(child, child_slot(r.c, D, 0) << 2, 0, 0);
+    // an empty gather, so that every path into the loop has the same loads in
+    // flight behind the entry (the compiler then waits for the entry alone)
+    smp.issue(-1, 0.0f);
     while (true) {
-        // descend from (node, level L) to the leaf (data or empty) holding cell c;
-        // an internal entry below depth D or beyond the array is malformed and
-        // taken as empty
-        int e;
-        while (true) {
-            stk[L * kBlock] = node;
-            const int sft = D - 1 - L;
-            const int oct = (((r.c[0] >> sft) & 1) << 2) | (((r.c[1] >> sft) & 1) << 1) | ((r.c[2] >> sft) & 1);
-            e = __builtin_amdgcn_raw_buffer_load_b32(child, ((uint32_t)node << 5) | ((uint32_t)oct << 2), 0, 0);
-            ++L;
-            const bool malformed = (e > 0) & ((L >= D) | (e >= tr.n_nodes));
-            bad |= malformed;
-            e = malformed ? 0 : e;
-            if (e <= 0) break;
-            node = e;
+        // finish the descent: e is the entry of the level-(L+1) cell holding c
+        ++L;
+        bool malformed = (e > 0) & ((L >= D) | (e >= tr.n_nodes));
+        bad |= malformed;
+        e = malformed ? 0 : e;
+        if (e > 0) {
+            // further levels (each waits for its own load, and for any older one)
+            while (true) {
+                node = e;
+                stk[L * kBlock] = node;
+                e = __builtin_amdgcn_raw_buffer_load_b32(
+                    child, ((uint32_t)node << 5) | (child_slot(r.c, D, L) << 2), 0, 0);
+                ++L;
+                malformed = (e > 0) & ((L >= D) | (e >= tr.n_nodes));
+                bad |= malformed;
+                e = malformed ? 0 : e;
+                if (e <= 0) break;
+            }
         }
         int leaf = -1 - e;
         if (leaf >= tr.n_leaves) {
@@ -247,22 +308,12 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
             sk[k] = ((double)(lo[k] + (pos[k] ? csz : 0)) - r.og[k]) * r.inv[k];
         }
         const double se = fmax(fmin(fmin(sk[0], sk[1]), sk[2]), r.s);
+        const float delta = (float)((se - r.s) * r.len);
         ++steps;
-        if (pending) {
-            pending = false;
-            if (smp.consume()) break;
-        }
-        if (leaf >= 0) {
-            const float delta = (float)((se - r.s) * r.len);
-            if (delta > 0.0f) {
-                smp.issue(leaf, delta);
-                pending = true;
-            }
-        }
-        // move across the exit face(s): axes whose face is reached step to the
-        // neighbouring cell; the others take the finest cell of the exit point,
-        // kept inside the current cube and never moving against the ray
-        // (truncation equals floor here: the result is clamped to >= lo >= 0)
+        // next cell: axes whose face is reached step to the neighbouring cell;
+        // the others take the finest cell of the exit point, kept inside the
+        // current cube and never moving against the ray (truncation equals
+        // floor here: the result is clamped to >= lo >= 0)
         bool out = false;
         int nc[3];
 #pragma unroll
@@ -275,19 +326,37 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
             out |= cross & ((stepped < 0) | (stepped >= N));
         }
         r.s = se;
-        if (out) break;
-        if (steps >= max_steps) {
-            bad = true;
-            break;
+        const bool capped = !out & (steps >= max_steps);
+        bad |= capped;
+        const bool last = out | capped;
+        // prefetch the next cell's entry, from the deepest common ancestor: the
+        // cells agree on the coordinate bits above the highest differing one.
+        // The load is issued on every path (out of range after the last step)
+        // so the compiler can count the loads in flight exactly.
+        uint32_t pf = tr_child_end;
+        if (!last) {
+            const int diff = (r.c[0] ^ nc[0]) | (r.c[1] ^ nc[1]) | (r.c[2] ^ nc[2]);
+            L = D - 32 + __clz(diff);
+            node = stk[L * kBlock];
+            r.c[0] = nc[0];
+            r.c[1] = nc[1];
+            r.c[2] = nc[2];
+            pf = ((uint32_t)node << 5) | (child_slot(r.c, D, L) << 2);
         }
-        // deepest common ancestor: the cells agree on the coordinate bits above
-        // the highest differing one
-        const int diff = (r.c[0] ^ nc[0]) | (r.c[1] ^ nc[1]) | (r.c[2] ^ nc[2]);
-        L = D - 32 + __clz(diff);
-        node = stk[L * kBlock];
-        r.c[0] = nc[0];
-        r.c[1] = nc[1];
-        r.c[2] = nc[2];
+        e = __builtin_amdgcn_raw_buffer_load_b32(child, pf, 0, 0);
+        // composite the previous sample (its loads precede the prefetch)
+        bool stop = false;
+        if (pending) {
+            pending = false;
+            stop = smp.consume();
+        }
+        // start this cell's gather; lanes without a sample load nothing.  The
+        // walk ends only at the bottom of the body, so every path back to the
+        // top has issued the same loads.
+        const bool take = !stop & (leaf >= 0) & (delta > 0.0f);
+        smp.issue(take ? leaf : -1, delta);
+        pending = take;
+        if (last | stop) break;
     }
     if (pending) smp.consume();
     // a lane that met a malformed entry or the step cap is counted once
@@ -308,9 +377,8 @@ __device__ __forceinline__ float dot_channel(const uint32_t (&w)[NW], int base, 
 template <typename T, int K, int VEC, int NL>
 struct FwdSampler {
     static constexpr int NW = Words<T, NL>::N;
-    const T* sig;
-    const char* shb;
-    size_t rec_bytes;
+    __amdgpu_buffer_rsrc_t sig, shb;
+    uint32_t sig_end, sh_end, rec_bytes;
     float stopT;
     float Y[K];
     float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, Tl = 1.0f;
@@ -319,9 +387,10 @@ struct FwdSampler {
     float raw, delta;
     uint32_t w[NW];
 
+    // leaf < 0: no sample; the out-of-range offsets load zeros without memory traffic
     __device__ __forceinline__ void issue(int leaf, float d) {
-        raw = load_sigma(sig, leaf);
-        load_words<T, NL, VEC>(shb + (size_t)leaf * rec_bytes, w);
+        raw = sigma_buf(sig, leaf < 0 ? sig_end : (uint32_t)leaf * (uint32_t)sizeof(T), (T*)nullptr);
+        load_words_buf<T, NL, VEC>(shb, leaf < 0 ? sh_end : (uint32_t)leaf * rec_bytes, w);
         delta = d;
     }
     __device__ __forceinline__ bool consume() {
@@ -350,9 +419,11 @@ __device__ __forceinline__ void render_one(const KTree& tr, const KOpts& op, con
     Ray r;
     if (ray_setup(tr, o, d, r)) {
         FwdSampler<T, K, VEC, NL> smp;
-        smp.sig = static_cast<const T*>(tr.sigma);
-        smp.shb = static_cast<const char*>(tr.sh);
-        smp.rec_bytes = (size_t)tr.stride * sizeof(T);
+        smp.sig = raw_rsrc(tr.sigma, tr.sigma_bytes);
+        smp.shb = raw_rsrc(tr.sh, tr.sh_bytes);
+        smp.sig_end = tr.sigma_bytes;
+        smp.sh_end = tr.sh_bytes;
+        smp.rec_bytes = (uint32_t)tr.stride * (uint32_t)sizeof(T);
         smp.stopT = op.stop_T;
         sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], smp.Y);
         steps = march(tr, r, op.max_steps, stk, smp);
@@ -480,9 +551,8 @@ __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
 template <int K, int VEC, int NL>
 struct BwdSampler {
     static constexpr int NW = Words<float, NL>::N;
-    const float* sig;
-    const char* shb;
-    size_t rec_bytes;
+    __amdgpu_buffer_rsrc_t sig, shb;
+    uint32_t sig_end, sh_end, rec_bytes;
     int stride;
     float stopT;
     float Y[K];
@@ -497,8 +567,8 @@ struct BwdSampler {
 
     __device__ __forceinline__ void issue(int l, float d) {
         leaf = l;
-        raw = load_sigma(sig, l);
-        load_words<float, NL, VEC>(shb + (size_t)l * rec_bytes, w);
+        raw = sigma_buf(sig, l < 0 ? sig_end : (uint32_t)l * 4u, (float*)nullptr);
+        load_words_buf<float, NL, VEC>(shb, l < 0 ? sh_end : (uint32_t)l * rec_bytes, w);
         delta = d;
     }
     __device__ __forceinline__ bool consume() {
@@ -556,9 +626,11 @@ __global__ __launch_bounds__(kBlock) void k_backward(KTree tr, int64_t n, int64_
     smp.C0 = rgb_fwd[3 * i];
     smp.C1 = rgb_fwd[3 * i + 1];
     smp.C2 = rgb_fwd[3 * i + 2];
-    smp.sig = static_cast<const float*>(tr.sigma);
-    smp.shb = static_cast<const char*>(tr.sh);
-    smp.rec_bytes = (size_t)tr.stride * sizeof(float);
+    smp.sig = raw_rsrc(tr.sigma, tr.sigma_bytes);
+    smp.shb = raw_rsrc(tr.sh, tr.sh_bytes);
+    smp.sig_end = tr.sigma_bytes;
+    smp.sh_end = tr.sh_bytes;
+    smp.rec_bytes = (uint32_t)tr.stride * 4u;
     smp.stride = tr.stride;
     smp.stopT = op.stop_T;
     smp.gsig = gsig;
