@@ -31,6 +31,36 @@ N_POSES = 200
 STOP_T = 1e-4
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "render_camera_depth9_800x800_hbm_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2103_14024_amd", "csrc", "po_kernels.hip")
+
+
+def kernel_hash() -> str:
+    import hashlib
+
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def counter_traffic(dtype: str):
+    """HBM bytes per launch of the float32/float16 render kernel from the
+    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, scaled by
+    a plain copy), or None when the kernel source changed since."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    import re
+
+    h = re.search(r"kernel_source_sha256_16 = `([0-9a-f]+)`", text)
+    if h is None or h.group(1) != kernel_hash():
+        return None
+    vals = dict(re.findall(r"(hbm_bytes_per_launch_f(?:16|32)) = `(\d+)`", text))
+    v = vals.get("hbm_bytes_per_launch_" + dtype)
+    return float(v) if v else None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -246,6 +276,8 @@ def main():
     log(f"fp32: {r32['fps']:.1f} FPS, {r32['msamples_per_s']:.0f} Msamples/s, "
         f"{r32['samples_per_ray']:.2f} samples/ray, {r32['steps_per_ray']:.1f} steps/ray, "
         f"lane efficiency {r32['lane_efficiency']:.3f}")
+    tb = counter_traffic("f32")
+    traffic_gbps = None if tb is None else round(tb / (r32["ms_per_step"] * 1e-3) / 1e9, 1)
     out = {
         "metric": METRIC, "value": round(r32["fps"], 2), "unit": "FPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(r32["ms_per_step"], 4), "higher_is_better": True,
@@ -257,9 +289,10 @@ def main():
         "samples_per_ray": round(r32["samples_per_ray"], 3), "steps_per_ray": round(r32["steps_per_ray"], 2),
         "lane_efficiency": round(r32["lane_efficiency"], 4),
         "roofline": {"bound": "hbm", "achieved": round(r32["alg_gbps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(r32["alg_gbps"] / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "frac": round(r32["alg_gbps"] / HBM_PEAK_GBPS, 4), "traffic": traffic_gbps,
                      "kernel": "k_render_camera<float,16,16,48,1>",
-                     "alg_bytes_per_launch": int(r32["alg_bytes_per_launch"])},
+                     "alg_bytes_per_launch": int(r32["alg_bytes_per_launch"]),
+                     "hbm_bytes_per_launch": None if tb is None else int(tb)},
         "paper_context": {"fps": 167.68, "hardware": "Tesla V100", "workload": "NeRF-synthetic real scenes"},
     }
     del tree32
@@ -268,9 +301,12 @@ def main():
         tree16 = po.Tree.from_scene(scene, dtype="f16")
         r16 = measure(po, tree16, cams, args.steps, args.warmup, stream)
         log(f"fp16: {r16['fps']:.1f} FPS, {r16['msamples_per_s']:.0f} Msamples/s")
+        t16 = counter_traffic("f16")
         out["fp16"] = {"fps": round(r16["fps"], 2), "ms_per_step": round(r16["ms_per_step"], 4),
                        "msamples_per_s": round(r16["msamples_per_s"], 1),
-                       "alg_gbps": round(r16["alg_gbps"], 1), "speedup_vs_fp32": round(r16["fps"] / r32["fps"], 3)}
+                       "alg_gbps": round(r16["alg_gbps"], 1), "alg_frac": round(r16["alg_gbps"] / HBM_PEAK_GBPS, 4),
+                       "hbm_gbps": None if t16 is None else round(t16 / (r16["ms_per_step"] * 1e-3) / 1e9, 1),
+                       "speedup_vs_fp32": round(r16["fps"] / r32["fps"], 3)}
         del tree16
     if not args.no_train:
         log("differentiation: direct octree optimisation")
