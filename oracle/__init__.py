@@ -56,6 +56,8 @@ def _load():
     L.orc_ray_segments.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_int64, _dp, _dp, _i64p]
     L.orc_render_rays.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp, _dp, _dp, ctypes.c_double,
                                   _dp, _dp, _i64p, _dp]
+    L.orc_render_rays_view.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp, _dp, _dp, ctypes.c_double,
+                                       ctypes.c_uint32, _dp, _dp, _dp, _i64p, _dp]
     L.orc_camera_rays.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, _dp, _dp]
     L.orc_render_camera.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -155,6 +157,23 @@ class OracleTree:
         L.orc_render_rays(self._h, n, _p(o), _p(d), _p(_d(bg)), float(gamma), _p(rgb), _p(T),
                           _p(ns, _i64p), _p(sm))
         return rgb, T, ns, sm
+
+    def render_view(self, o, d, bg=(1.0, 1.0, 1.0), gamma=0.0, sh_off=0, clip=None):
+        """Viewer render: returns (rgb (n,3), T (n,), n_samples (n,), depth (n,)).
+
+        sh_off: bit k drops basis function k; clip: (nx, ny, nz, w), keep n.x + w >= 0."""
+        L = _load()
+        o = _d(o).reshape(-1, 3)
+        d = _d(d).reshape(-1, 3)
+        n = o.shape[0]
+        rgb = np.zeros((n, 3), np.float64)
+        T = np.zeros(n, np.float64)
+        ns = np.zeros(n, np.int64)
+        dep = np.zeros(n, np.float64)
+        cp = None if clip is None else _p(_d(clip).reshape(4))
+        L.orc_render_rays_view(self._h, n, _p(o), _p(d), _p(_d(bg)), float(gamma), int(sh_off) & 0xffffffff,
+                               cp, _p(rgb), _p(T), _p(ns, _i64p), _p(dep))
+        return rgb, T, ns, dep
 
     def render_camera(self, c2w, W, H, fx, fy, cx, cy, bg=(1.0, 1.0, 1.0), gamma=0.0):
         """Returns (rgb (H,W,3), T (H,W), n_samples (H,W))."""

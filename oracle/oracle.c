@@ -24,7 +24,10 @@
  *     transmittance falls below a threshold (Sec. 4.2, "Rendering");
  *   - the colour and density derivatives of App. B.3, evaluated with the
  *     two-pass scheme of the Remark there: the first pass yields the full
- *     colour, the second subtracts a running prefix.
+ *     colour, the second subtracts a running prefix;
+ *   - the viewer outputs of Sec. 5.5 ("Interactive demos"): a depth map, a
+ *     cross-section (slicing plane) and renders with a subset of the SH
+ *     components.
  *
  * Readings where the paper is silent (each is also listed in the design notes):
  *   - SH: P_l^m includes the Condon-Shortley phase; the argument of the basis
@@ -36,6 +39,13 @@
  *     belongs to the half-open cell [lo, hi) on that axis.
  *   - Camera: pinhole, pixel centres, OpenGL camera frame (-z forward, +y up),
  *     camera-to-world matrix row-major 3x4.
+ *   - Depth map: the expected distance at which the ray terminates under the
+ *     piecewise-constant density, integral of t sigma(t) T(t) dt over the
+ *     segments composited (up to the early stop), with no normalisation; the
+ *     alpha map is 1 - T.
+ *   - Slicing: only the part of each ray inside the half-space n.x + w >= 0
+ *     is rendered (clip = (n, w)); all-zero clip keeps everything.
+ *   - SH subsets: bit k of sh_off drops basis function k from every channel.
  */
 #include <math.h>
 #include <stdint.h>
@@ -306,9 +316,27 @@ static void visit(const orc_tree* t, int32_t node, const double* lo, double size
     }
 }
 
-/* Segments of the ray o + t d (d normalised here), t >= 0, through the box. */
-static void ray_segments(const orc_tree* t, const double* o, const double* d_in, double* dn,
-                         seglist* out) {
+/* Keeps the part of [a, b] (parameters along the unit direction dn from o)
+ * inside the half-space n.x + w >= 0, clip = (n_x, n_y, n_z, w). */
+static void clip_interval(const double* clip, const double* o, const double* dn, double* a,
+                          double* b) {
+    double p0 = clip[0] * o[0] + clip[1] * o[1] + clip[2] * o[2] + clip[3];
+    double pd = clip[0] * dn[0] + clip[1] * dn[1] + clip[2] * dn[2];
+    if (pd > 0.0) {
+        double t = -p0 / pd; /* entering the half-space at t */
+        if (t > *a) *a = t;
+    } else if (pd < 0.0) {
+        double t = -p0 / pd; /* leaving it at t */
+        if (t < *b) *b = t;
+    } else if (p0 < 0.0) {
+        *b = *a; /* parallel to the plane, outside */
+    }
+}
+
+/* Segments of the ray o + t d (d normalised here), t >= 0, through the box,
+ * optionally restricted to the half-space of clip (NULL: no restriction). */
+static void ray_segments(const orc_tree* t, const double* o, const double* d_in,
+                         const double* clip, double* dn, seglist* out) {
     double n = sqrt(d_in[0] * d_in[0] + d_in[1] * d_in[1] + d_in[2] * d_in[2]);
     for (int k = 0; k < 3; ++k) dn[k] = d_in[k] / n;
     out->n = 0;
@@ -320,6 +348,7 @@ static void ray_segments(const orc_tree* t, const double* o, const double* d_in,
     double a, b;
     slab(o, dn, lo, hi, &a, &b);
     if (a < 0.0) a = 0.0;
+    if (clip) clip_interval(clip, o, dn, &a, &b);
     if (b - a > 0.0) visit(t, 0, lo, 2.0 * t->half, a, b, o, dn, out);
 }
 
@@ -329,7 +358,7 @@ int64_t orc_ray_segments(const orc_tree* t, const double* o, const double* d, in
                          double* seg_a, double* seg_b, int64_t* seg_leaf) {
     seglist L = {0};
     double dn[3];
-    ray_segments(t, o, d, dn, &L);
+    ray_segments(t, o, d, NULL, dn, &L);
     for (int64_t i = 0; i < L.n && i < cap; ++i) {
         seg_a[i] = L.s[i].a;
         seg_b[i] = L.s[i].b;
@@ -357,14 +386,19 @@ static void leaf_colour(const orc_tree* t, int64_t leaf, const double* Y, double
 }
 
 /* Renders one ray.  Returns colour, final transmittance, number of data
- * samples composited and the largest clamped density met. */
+ * samples composited, the largest clamped density met and the expected
+ * termination distance.  sh_off drops basis functions; clip (or NULL) is the
+ * slicing half-space. */
 static void render_one(const orc_tree* t, const double* o, const double* d, const double* bg,
-                       double gamma, seglist* L, double* Y, double* rgb, double* T_out,
-                       int64_t* ns_out, double* smax_out) {
+                       double gamma, uint32_t sh_off, const double* clip, seglist* L, double* Y,
+                       double* rgb, double* T_out, int64_t* ns_out, double* smax_out,
+                       double* depth_out) {
     double dn[3];
-    ray_segments(t, o, d, dn, L);
+    ray_segments(t, o, d, clip, dn, L);
     orc_sh_basis(t->lmax, dn, Y);
-    double C[3] = {0, 0, 0}, T = 1.0, smax = 0.0;
+    for (int k = 0; k < t->ncoef && k < 32; ++k)
+        if ((sh_off >> k) & 1u) Y[k] = 0.0;
+    double C[3] = {0, 0, 0}, T = 1.0, smax = 0.0, depth = 0.0;
     int64_t ns = 0;
     for (int64_t i = 0; i < L->n; ++i) {
         int64_t leaf = L->s[i].leaf;
@@ -376,6 +410,12 @@ static void render_one(const orc_tree* t, const double* o, const double* d, cons
         double c[3];
         leaf_colour(t, leaf, Y, c);
         for (int ch = 0; ch < 3; ++ch) C[ch] += T * alpha * c[ch];
+        /* termination distance: with T(x) = T exp(-sig (x - a)) on [a, b],
+         * the integral of x sig T(x) is T (a alpha + alpha / sig - delta exp(-tau)) */
+        if (sig > 0.0) {
+            double a = L->s[i].a;
+            depth += T * (a * alpha + alpha / sig - delta * exp(-tau));
+        }
         T *= exp(-tau);
         ++ns;
         if (sig > smax) smax = sig;
@@ -385,6 +425,7 @@ static void render_one(const orc_tree* t, const double* o, const double* d, cons
     *T_out = T;
     *ns_out = ns;
     *smax_out = smax;
+    if (depth_out) *depth_out = depth;
 }
 
 /* Renders n rays (o, d: n x 3).  Any of T_out, ns_out, smax_out may be NULL.
@@ -400,10 +441,35 @@ void orc_render_rays(const orc_tree* t, int64_t n, const double* o, const double
         for (int64_t r = 0; r < n; ++r) {
             double T, smax;
             int64_t ns;
-            render_one(t, o + 3 * r, d + 3 * r, bg, gamma, &L, Y, rgb + 3 * r, &T, &ns, &smax);
+            render_one(t, o + 3 * r, d + 3 * r, bg, gamma, 0u, NULL, &L, Y, rgb + 3 * r, &T, &ns,
+                       &smax, NULL);
             if (T_out) T_out[r] = T;
             if (ns_out) ns_out[r] = ns;
             if (smax_out) smax_out[r] = smax;
+        }
+        free(L.s);
+    }
+}
+
+/* Viewer render (Sec. 5.5): as orc_render_rays, with basis functions dropped
+ * by sh_off, the slicing half-space clip (4 values, or NULL) and the expected
+ * termination distance in depth_out.  Any output but rgb may be NULL. */
+void orc_render_rays_view(const orc_tree* t, int64_t n, const double* o, const double* d,
+                          const double* bg, double gamma, uint32_t sh_off, const double* clip,
+                          double* rgb, double* T_out, int64_t* ns_out, double* depth_out) {
+#pragma omp parallel
+    {
+        seglist L = {0};
+        double Y[81];
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t r = 0; r < n; ++r) {
+            double T, smax, dep;
+            int64_t ns;
+            render_one(t, o + 3 * r, d + 3 * r, bg, gamma, sh_off, clip, &L, Y, rgb + 3 * r, &T,
+                       &ns, &smax, &dep);
+            if (T_out) T_out[r] = T;
+            if (ns_out) ns_out[r] = ns;
+            if (depth_out) depth_out[r] = dep;
         }
         free(L.s);
     }
@@ -461,7 +527,7 @@ void orc_grad(const orc_tree* t, int64_t n, const double* o, const double* d,
     for (int64_t r = 0; r < n; ++r) {
         double C[3], Tf, smax;
         int64_t ns;
-        render_one(t, o + 3 * r, d + 3 * r, bg, gamma, &L, Y, C, &Tf, &ns, &smax);
+        render_one(t, o + 3 * r, d + 3 * r, bg, gamma, 0u, NULL, &L, Y, C, &Tf, &ns, &smax, NULL);
         /* L and Y still hold this ray's segments and basis. */
         const double* gr = g + 3 * r;
         double P[3] = {0, 0, 0}, T = 1.0;
