@@ -58,6 +58,7 @@ def _load():
                                   _dp, _dp, _i64p, _dp]
     L.orc_render_rays_view.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp, _dp, _dp, ctypes.c_double,
                                        ctypes.c_uint32, _dp, _dp, _dp, _i64p, _dp]
+    L.orc_leaf_weights.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp]
     L.orc_camera_rays.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, _dp, _dp]
     L.orc_render_camera.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -196,6 +197,18 @@ class OracleTree:
         gsh = np.zeros((self.n_leaves, 3, self.K), np.float64)
         L.orc_grad(self._h, o.shape[0], _p(o), _p(d), _p(_d(bg)), float(gamma), _p(g), _p(gs), _p(gsh))
         return gs, gsh
+
+    def leaf_weights(self, o, d, gamma=0.0, mode=0, weight=None):
+        """Largest ray weight per leaf (n_leaves,) over the rays (o, d): mode 0
+        1 - exp(-sigma delta), mode 1 T (1 - exp(-sigma delta)); weight, if
+        given, is raised in place (float64) and returned."""
+        L = _load()
+        o = _d(o).reshape(-1, 3)
+        d = _d(d).reshape(-1, 3)
+        w = np.zeros(self.n_leaves, np.float64) if weight is None else weight
+        assert w.dtype == np.float64 and w.shape == (self.n_leaves,) and w.flags.c_contiguous
+        L.orc_leaf_weights(self._h, o.shape[0], _p(o), _p(d), float(gamma), int(mode), _p(w))
+        return w
 
     def segments(self, o, d, cap=1 << 16):
         """Segments of one ray: (a (m,), b (m,), leaf (m,)); leaf -1 is empty space."""

@@ -27,7 +27,10 @@
  *     colour, the second subtracts a running prefix;
  *   - the viewer outputs of Sec. 5.5 ("Interactive demos"): a depth map, a
  *     cross-section (slicing plane) and renders with a subset of the SH
- *     components.
+ *     components;
+ *   - the visibility filter of the conversion (Sec. 4.2, "Filtering"): the
+ *     largest ray weight each leaf receives over the rays of a set of alpha
+ *     renders.
  *
  * Readings where the paper is silent (each is also listed in the design notes):
  *   - SH: P_l^m includes the Condon-Shortley phase; the argument of the basis
@@ -46,6 +49,10 @@
  *   - Slicing: only the part of each ray inside the half-space n.x + w >= 0
  *     is rendered (clip = (n, w)); all-zero clip keeps everything.
  *   - SH subsets: bit k of sh_off drops basis function k from every channel.
+ *   - Filter weight: the printed 1 - exp(-sigma delta) of a segment (mode 0),
+ *     or its contribution T (1 - exp(-sigma delta)) (mode 1); the alpha
+ *     renders stop early like every render, which is what removes voxels
+ *     hidden behind opaque ones.
  */
 #include <math.h>
 #include <stdint.h>
@@ -556,6 +563,37 @@ void orc_grad(const orc_tree* t, int64_t n, const double* o, const double* d,
             }
             if (raw > 0.0) grad_sigma[leaf] += gs;
             T = Tn;
+        }
+    }
+    free(L.s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Visibility filter (Sec. 4.2, "Filtering")                                 */
+/* ------------------------------------------------------------------------ */
+
+/* For rays (o, d) rendered as alpha maps, raises weight[leaf] (n_leaves, the
+ * caller initialises it) to the largest weight of any data segment of the
+ * leaf: mode 0 the segment's 1 - exp(-sigma delta), mode 1 its contribution
+ * T (1 - exp(-sigma delta)).  Segments after the early stop (T < gamma) are
+ * not rendered and give nothing.  Single-threaded. */
+void orc_leaf_weights(const orc_tree* t, int64_t n, const double* o, const double* d,
+                      double gamma, int mode, double* weight) {
+    seglist L = {0};
+    for (int64_t r = 0; r < n; ++r) {
+        double dn[3];
+        ray_segments(t, o + 3 * r, d + 3 * r, NULL, dn, &L);
+        double T = 1.0;
+        for (int64_t i = 0; i < L.n; ++i) {
+            int64_t leaf = L.s[i].leaf;
+            if (leaf < 0) continue;
+            double sig = fmax(t->sigma[leaf], 0.0);
+            double tau = sig * (L.s[i].b - L.s[i].a);
+            double alpha = -expm1(-tau);
+            double w = mode ? T * alpha : alpha;
+            if (w > weight[leaf]) weight[leaf] = w;
+            T *= exp(-tau);
+            if (T < gamma) break;
         }
     }
     free(L.s);
