@@ -52,6 +52,9 @@ def _load():
     L.orc_tree_n_nodes.restype = ctypes.c_int64
     L.orc_tree_n_nodes.argtypes = [ctypes.c_void_p]
     L.orc_sh_basis.argtypes = [ctypes.c_int, _dp, _dp]
+    L.orc_sg_basis.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+    L.orc_tree_set_sg.restype = ctypes.c_int
+    L.orc_tree_set_sg.argtypes = [ctypes.c_void_p, _dp]
     L.orc_ray_segments.restype = ctypes.c_int64
     L.orc_ray_segments.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_int64, _dp, _dp, _i64p]
     L.orc_render_rays.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp, _dp, _dp, ctypes.c_double,
@@ -100,6 +103,17 @@ def sh_basis(lmax: int, dirs) -> np.ndarray:
     return out
 
 
+def sg_basis(lobes, dirs) -> np.ndarray:
+    """Spherical-Gaussian values (n, K) at directions (n, 3) for lobes (K, 4) = (axis, bandwidth)."""
+    L = _load()
+    lb = _d(lobes).reshape(-1, 4)
+    dirs = _d(dirs).reshape(-1, 3)
+    out = np.zeros((dirs.shape[0], lb.shape[0]), np.float64)
+    for i in range(dirs.shape[0]):
+        L.orc_sg_basis(lb.shape[0], _p(lb), _p(dirs[i]), _p(out[i]))
+    return out
+
+
 def camera_rays(c2w, W, H, fx, fy, cx, cy):
     """Pixel-centre pinhole rays (origins, directions), each (H*W, 3) float64."""
     L = _load()
@@ -115,10 +129,11 @@ class OracleTree:
 
     cells: (n, 4) int (level, i, j, k); sigma: (n,) raw densities;
     sh: (n, 3, K) coefficients, K = (lmax+1)^2, channel-major.
-    Values are promoted exactly to float64.
+    lobes: None for the SH basis, or (K, 4) spherical-Gaussian lobes (axis,
+    bandwidth) that replace it.  Values are promoted exactly to float64.
     """
 
-    def __init__(self, depth, lmax, center, half, cells, sigma, sh):
+    def __init__(self, depth, lmax, center, half, cells, sigma, sh, lobes=None):
         L = _load()
         self.depth, self.lmax = int(depth), int(lmax)
         self.K = (self.lmax + 1) ** 2
@@ -134,6 +149,10 @@ class OracleTree:
             raise ValueError("oracle tree: " + err.value.decode())
         self._h = ctypes.c_void_p(h)
         self.n_leaves = n
+        if lobes is not None:
+            lb = _d(lobes).reshape(self.K, 4)
+            if L.orc_tree_set_sg(self._h, _p(lb)) != 0:
+                raise ValueError("oracle tree: SG lobe axes must be non-zero")
 
     def __del__(self):
         h = getattr(self, "_h", None)

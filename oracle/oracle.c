@@ -32,6 +32,9 @@
  *     largest ray weight each leaf receives over the rays of a set of alpha
  *     renders.
  *
+ *   - the spherical-Gaussian colour basis of App. B.1 (learnable lobes,
+ *     global to the tree) in place of the SH.
+ *
  * Readings where the paper is silent (each is also listed in the design notes):
  *   - SH: P_l^m includes the Condon-Shortley phase; the argument of the basis
  *     is the unit propagation direction of the ray; theta is measured from +z,
@@ -49,6 +52,9 @@
  *   - Slicing: only the part of each ray inside the half-space n.x + w >= 0
  *     is rendered (clip = (n, w)); all-zero clip keeps everything.
  *   - SH subsets: bit k of sh_off drops basis function k from every channel.
+ *   - SG basis: G_j(d) = exp(lambda_j (d . p_j / |p_j| - 1)) with the lobe
+ *     axis a 3-vector (the paper's "p in R^2" parametrises the sphere), one
+ *     set of lobes per tree, the colour the sigmoid of sum_j k_j G_j(d).
  *   - Filter weight: the printed 1 - exp(-sigma delta) of a segment (mode 0),
  *     or its contribution T (1 - exp(-sigma delta)) (mode 1); the alpha
  *     renders stop early like every render, which is what removes voxels
@@ -89,6 +95,7 @@ typedef struct {
     int64_t n_leaves;
     double* sigma;          /* [leaf]            raw density before clamping */
     double* sh;             /* [leaf][3][ncoef]  per-channel SH coefficients */
+    double* sg;             /* NULL: SH basis; else [ncoef][4] SG lobes (axis, bandwidth) */
 } orc_tree;
 
 static int32_t new_node(orc_tree* t) {
@@ -110,6 +117,7 @@ void orc_tree_free(orc_tree* t) {
     free(t->nodes);
     free(t->sigma);
     free(t->sh);
+    free(t->sg);
     free(t);
 }
 
@@ -211,6 +219,44 @@ static double assoc_legendre(int l, int m, double x) {
         pm1 = p2;
     }
     return p2;
+}
+
+/* Spherical-Gaussian basis (App. B.1, "Spherical Gaussians"): n values
+ * G_j(d) = exp(lambda_j (d . p_j - 1)) at the unit direction d, with unit
+ * axes p_j = lobes[4j..4j+2] normalised here and bandwidths lambda_j =
+ * lobes[4j+3]. */
+void orc_sg_basis(int n, const double* lobes, const double* d_in, double* out) {
+    double dn = sqrt(d_in[0] * d_in[0] + d_in[1] * d_in[1] + d_in[2] * d_in[2]);
+    for (int j = 0; j < n; ++j) {
+        const double* q = lobes + 4 * j;
+        double pn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        double cosang = (d_in[0] * q[0] + d_in[1] * q[1] + d_in[2] * q[2]) / (dn * pn);
+        out[j] = exp(q[3] * (cosang - 1.0));
+    }
+}
+
+/* Switches the tree's colour basis to ncoef spherical Gaussians with the
+ * given lobes ([ncoef][4]: axis x, y, z, bandwidth).  Returns 0, or -1 for a
+ * zero axis. */
+int orc_tree_set_sg(orc_tree* t, const double* lobes) {
+    for (int j = 0; j < t->ncoef; ++j) {
+        const double* q = lobes + 4 * j;
+        if (!(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] > 0.0)) return -1;
+    }
+    double* c = (double*)malloc(sizeof(double) * 4 * (size_t)t->ncoef);
+    if (!c) return -1;
+    memcpy(c, lobes, sizeof(double) * 4 * (size_t)t->ncoef);
+    free(t->sg);
+    t->sg = c;
+    return 0;
+}
+
+void orc_sh_basis(int lmax, const double* d_in, double* out);
+
+/* Basis values of the tree's colour model at direction d. */
+static void colour_basis(const orc_tree* t, const double* d, double* Y) {
+    if (t->sg) orc_sg_basis(t->ncoef, t->sg, d, Y);
+    else orc_sh_basis(t->lmax, d, Y);
 }
 
 /* Writes the (lmax+1)^2 real SH values at direction d (normalised here) into
@@ -402,7 +448,7 @@ static void render_one(const orc_tree* t, const double* o, const double* d, cons
                        double* depth_out) {
     double dn[3];
     ray_segments(t, o, d, clip, dn, L);
-    orc_sh_basis(t->lmax, dn, Y);
+    colour_basis(t, dn, Y);
     for (int k = 0; k < t->ncoef && k < 32; ++k)
         if ((sh_off >> k) & 1u) Y[k] = 0.0;
     double C[3] = {0, 0, 0}, T = 1.0, smax = 0.0, depth = 0.0;
