@@ -76,16 +76,16 @@ def measure(po, tree, cams, steps, warmup, stream, aux_pass=True):
 
     img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     # per-pose samples and traversal steps, outside the timed region
-    aux = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    aux = torch.empty((H, W, po.AUX_WIDTH), dtype=torch.float32, device="cuda")
     samples, tsteps, wave_iters = [], [], []
     for cam in (cams if aux_pass else []):
         po.render_camera(tree, cam, stop_T=STOP_T, aux=True, out=img, aux_out=aux, stream=stream)
-        a = aux.view(-1, 3).sum(0).cpu()
-        samples.append(float(a[1]))
-        tsteps.append(float(a[2]))
+        a = aux.view(-1, po.AUX_WIDTH).sum(0).cpu()
+        samples.append(float(a[po.AUX_SAMPLES]))
+        tsteps.append(float(a[po.AUX_STEPS]))
         # SIMD efficiency of the traversal loop: a wave (8x8 pixels) runs as
         # many iterations as its slowest lane
-        st = aux[..., 2].view(H // 8, 8, W // 8, 8).amax(dim=(1, 3))
+        st = aux[..., po.AUX_STEPS].view(H // 8, 8, W // 8, 8).amax(dim=(1, 3))
         wave_iters.append(float(st.sum()) * 64)
     for i in range(warmup):
         po.render_camera(tree, cams[i % len(cams)], stop_T=STOP_T, out=img, stream=stream)

@@ -64,7 +64,7 @@ extern "C" {
 #endif
 
 #define PO_MAX_DEPTH 15
-#define PO_MAX_SH_DEGREE 3
+#define PO_MAX_SH_DEGREE 4
 #define PO_BATCH_MAX_JOBS 16
 #define PO_TILE 16 /* camera images are processed in 16 x 16 pixel tiles */
 
@@ -91,13 +91,31 @@ typedef struct {
     int32_t sh_stride;
 } po_tree_desc;
 
-/* Per-call rendering options. */
-#define PO_OUT_AUX 1u /* also write aux[ray][3] = {final transmittance, data samples, traversal steps} */
+/* Per-call rendering options.
+ *
+ * PO_OUT_AUX also writes aux[ray][4] = {final transmittance T, data samples,
+ * traversal steps, depth}.  1 - T is the alpha map.  depth is the expected
+ * termination distance of the viewer's depth map (Sec. 5.5): the sum over the
+ * composited data segments [a, b] of the integral of t sigma T(t) dt, with t
+ * the distance from the ray origin in world units; it is not normalised by
+ * the opacity (divide by 1 - T for the mean over the opaque part).
+ *
+ * sh_off and clip are the other viewer options of Sec. 5.5.  Bit k of sh_off
+ * drops SH basis function k (index l*l + l + m) from every channel, so the
+ * colour of a leaf is the sigmoid of the remaining terms; bits at or above K
+ * have no effect.  clip = (nx, ny, nz, w) is a slicing plane: only the part
+ * of each ray where nx*x + ny*y + nz*z + w >= 0 is rendered (all zero: the
+ * whole ray).  These options apply to rendering only; the backward pass
+ * rejects them.  A call that sets none of them and no PO_OUT_AUX runs the
+ * plain kernels. */
+#define PO_OUT_AUX 1u
 typedef struct {
     float bg[3];        /* background colour c_N (App. B.3) */
     float stop_T;       /* early stop once T < stop_T after a data segment (Sec. 4.2); 0 disables */
     int32_t max_steps;  /* cap on traversal steps per ray; 0 = 3*2^D + 8, which valid trees never reach */
     uint32_t flags;     /* PO_OUT_* */
+    uint32_t sh_off;    /* SH basis functions left out (bit k = function k); 0 = none */
+    float clip[4];      /* slicing half-space n.x + w >= 0; all zero = none */
 } po_render_opts;
 
 typedef struct {
@@ -153,7 +171,7 @@ po_status po_tree_destroy(po_tree* t);
 
 /* ------------------------------------------------------------------ render
  * po_render_rays: renders n rays into d_rgb[n][3]; with PO_OUT_AUX also
- * d_aux[n][3].  The colour is sum_i T_i (1 - exp(-sigma_i delta_i)) c_i +
+ * d_aux[n][4].  The colour is sum_i T_i (1 - exp(-sigma_i delta_i)) c_i +
  * T_N bg over the data segments met before the early stop (Sec. 3 eqn:quad,
  * App. B.3), c_i = sigmoid(sum_k sh[leaf][ch][k] Y_k(d)) (Sec. 4.1).
  * Errors: PO_ERR_INVALID (NULL tree/opts/arrays with n > 0, n < 0, bad
@@ -162,7 +180,7 @@ po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, co
                          const po_render_opts* opts, float* d_rgb, float* d_aux, void* stream);
 
 /* po_render_camera: renders a camera image into d_rgb[height][width][3]
- * (and d_aux[height][width][3] with PO_OUT_AUX).  width, height in
+ * (and d_aux[height][width][4] with PO_OUT_AUX).  width, height in
  * [1, 16384]; fx, fy non-zero.  Errors as for po_render_rays. */
 po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_render_opts* opts,
                            float* d_rgb, float* d_aux, void* stream);
@@ -186,8 +204,8 @@ po_status po_camera_rays(const po_camera* cam, float* d_origins, float* d_dirs, 
  * rule through the sigmoid and the SH basis).  Several rays may hit one
  * leaf, so accumulation uses float atomics and its summation order is not
  * deterministic.  Zero the outputs first when a fresh gradient is wanted.
- * Errors: PO_ERR_INVALID, PO_ERR_UNSUPPORTED (tree not PO_F32),
- * PO_ERR_DEVICE. */
+ * Errors: PO_ERR_INVALID, PO_ERR_UNSUPPORTED (tree not PO_F32, or viewer
+ * options sh_off / clip set), PO_ERR_DEVICE. */
 po_status po_render_rays_backward(const po_tree* t, int64_t n, const float* d_origins,
                                   const float* d_dirs, const po_render_opts* opts,
                                   const float* d_rgb_fwd, const float* d_grad_rgb,
@@ -230,6 +248,39 @@ typedef struct {
 po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream);
 /* Number of 16x16 tiles of a camera image. */
 po_status po_camera_tiles(const po_camera* cam, int32_t* n_tiles);
+
+/* --------------------------------------------------------------- filtering
+ * The visibility filter of the conversion from a dense density grid (Sec.
+ * 4.2, "Filtering"): alpha maps of the training views are rendered through
+ * the tree, every leaf keeps the largest weight of a segment in it, and the
+ * leaves whose weight stays below a threshold are removed before the octree
+ * is rebuilt (po_tree_leaf_cells, then po_builder_* on the kept cells).
+ *
+ * po_leaf_weights renders one camera (pixel-centre rays as po_render_camera,
+ * early stop and step cap from opts) and raises d_weight[n_leaves] in place
+ * to the largest weight of every data segment met: PO_WEIGHT_ALPHA the
+ * segment's 1 - exp(-sigma delta), as the paper states the weight;
+ * PO_WEIGHT_CONTRIB its contribution T (1 - exp(-sigma delta)) to the pixel.
+ * With either, the early stop leaves voxels hidden behind opaque ones at
+ * their initial weight.  d_weight must hold non-negative, non-NaN floats
+ * (zeros before the first camera); the maximum is taken with integer atomics
+ * on the float bits, so it does not depend on the order of rays or cameras.
+ * d_alpha (or NULL) receives the alpha map [height][width], 1 - T.  Only the
+ * densities are read; bg is ignored, and opts must not set flags, sh_off or
+ * a slicing plane.  Errors: PO_ERR_INVALID, PO_ERR_UNSUPPORTED (viewer
+ * options), PO_ERR_DEVICE. */
+#define PO_WEIGHT_ALPHA 0
+#define PO_WEIGHT_CONTRIB 1
+po_status po_leaf_weights(const po_tree* t, const po_camera* cam, const po_render_opts* opts, int32_t mode,
+                          float* d_weight, float* d_alpha, void* stream);
+
+/* po_tree_leaf_cells: host only.  Checks the child array as
+ * po_tree_validate does and writes h_cells[n_leaves][4] = (level, i, j, k),
+ * the cell of each leaf (coordinates in [0, 2^level), child slot 4x + 2y + z
+ * as in the builder); leaves that no entry references get (-1, -1, -1, -1).
+ * Errors: PO_ERR_INVALID, PO_ERR_TREE, PO_ERR_OOM. */
+po_status po_tree_leaf_cells(const po_tree_desc* desc, int64_t n_nodes, const int32_t* h_child, int64_t n_leaves,
+                             int32_t* h_cells);
 
 /* ----------------------------------------------------------------- errors
  * Device error counter: malformed child entries met and traversal step caps

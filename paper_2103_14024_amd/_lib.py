@@ -14,8 +14,9 @@ LIB_PATH = os.path.join(PKG, "libplenoctree.so")
 PO_OK, PO_ERR_INVALID, PO_ERR_TREE, PO_ERR_OOM, PO_ERR_DEVICE, PO_ERR_UNSUPPORTED = range(6)
 PO_F32, PO_F16 = 0, 1
 PO_OUT_AUX = 1
+PO_WEIGHT_ALPHA, PO_WEIGHT_CONTRIB = 0, 1
 PO_MAX_DEPTH = 15
-PO_MAX_SH_DEGREE = 3
+PO_MAX_SH_DEGREE = 4
 PO_BATCH_MAX_JOBS = 16
 PO_TILE = 16
 
@@ -27,7 +28,7 @@ class po_tree_desc(ctypes.Structure):
 
 class po_render_opts(ctypes.Structure):
     _fields_ = [("bg", ctypes.c_float * 3), ("stop_T", ctypes.c_float), ("max_steps", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("sh_off", ctypes.c_uint32), ("clip", ctypes.c_float * 4)]
 
 
 class po_camera(ctypes.Structure):
@@ -70,6 +71,8 @@ _SIGS = {
     "po_camera_rays": [ctypes.POINTER(po_camera), _P, _P, _P],
     "po_mse_grad": [_I64, _P, _P, ctypes.c_float, _P, _P, _P],
     "po_sgd_step": [_I64, _P, _P, ctypes.c_float, _I32, _P],
+    "po_leaf_weights": [_P, ctypes.POINTER(po_camera), ctypes.POINTER(po_render_opts), _I32, _P, _P, _P],
+    "po_tree_leaf_cells": [ctypes.POINTER(po_tree_desc), _I64, _P, _I64, _P],
     "po_device_errors": [ctypes.POINTER(_I64)],
     "po_device_errors_reset": [],
 }

@@ -70,6 +70,8 @@ po_status check_opts(const po_render_opts* o) {
     if (!(o->stop_T >= 0.0f) || !finite(o->stop_T)) return fail(PO_ERR_INVALID, "stop_T must be finite and >= 0");
     if (o->max_steps < 0) return fail(PO_ERR_INVALID, "max_steps must be >= 0");
     if (o->flags & ~PO_OUT_AUX) return fail(PO_ERR_INVALID, "unknown flags 0x%x", o->flags);
+    for (int k = 0; k < 4; ++k)
+        if (!finite(o->clip[k])) return fail(PO_ERR_INVALID, "slicing plane must be finite");
     return PO_OK;
 }
 
@@ -79,6 +81,8 @@ KOpts kopts(const po_tree* t, const po_render_opts* o) {
     k.stop_T = o->stop_T;
     k.max_steps = o->max_steps ? o->max_steps : 3 * (1 << t->desc.depth) + 8;
     k.flags = o->flags;
+    k.sh_off = o->sh_off;
+    for (int i = 0; i < 4; ++i) k.clip[i] = o->clip[i];
     return k;
 }
 
@@ -320,6 +324,41 @@ po_status po_tree_validate(const po_tree_desc* desc, int64_t n_nodes, const int3
     return ok();
 }
 
+po_status po_tree_leaf_cells(const po_tree_desc* desc, int64_t n_nodes, const int32_t* h_child, int64_t n_leaves,
+                             int32_t* h_cells) {
+    if (po_status s = po_tree_validate(desc, n_nodes, h_child, n_leaves, nullptr)) return s;
+    if (!h_cells && n_leaves > 0) return fail(PO_ERR_INVALID, "cells array is NULL");
+    for (int64_t i = 0; i < 4 * n_leaves; ++i) h_cells[i] = -1;
+    try {
+        // breadth-first from the root with each node's cell (level, i, j, k)
+        struct Item {
+            int32_t node, level, i, j, k;
+        };
+        std::vector<Item> queue;
+        queue.reserve((size_t)n_nodes);
+        queue.push_back({0, 0, 0, 0, 0});
+        for (size_t h = 0; h < queue.size(); ++h) {
+            const Item v = queue[h];
+            for (int c = 0; c < 8; ++c) {
+                const int32_t e = h_child[(int64_t)v.node * 8 + c];
+                const Item ch = {e, v.level + 1, 2 * v.i + ((c >> 2) & 1), 2 * v.j + ((c >> 1) & 1), 2 * v.k + (c & 1)};
+                if (e > 0) {
+                    queue.push_back(ch);
+                } else if (e < 0) {
+                    int32_t* out = h_cells + 4 * (-(int64_t)e - 1);
+                    out[0] = ch.level;
+                    out[1] = ch.i;
+                    out[2] = ch.j;
+                    out[3] = ch.k;
+                }
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(PO_ERR_OOM, "leaf cell walk allocation");
+    }
+    return ok();
+}
+
 po_status po_tree_bind(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
                        const void* d_sigma, const void* d_sh, po_tree** out) {
     if (po_status s = check_desc(desc)) return s;
@@ -411,7 +450,7 @@ po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_rend
     j.tile_begin = 0;
     j.block_begin = 0;
     j.tiles_x = (cam->width + PO_TILE - 1) / PO_TILE;
-    hipError_t e = po_launch_camera_jobs(t, 1, &j, 4 * tiles_of(cam), (hipStream_t)stream);
+    hipError_t e = po_launch_camera_jobs(t, 1, &j, 4 * tiles_of(cam), po_view_opts(j.op, j.aux), (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "render_camera launch");
     return ok();
 }
@@ -422,6 +461,8 @@ po_status po_render_rays_backward(const po_tree* t, int64_t n, const float* d_or
     if (!t) return fail(PO_ERR_INVALID, "tree is NULL");
     if (po_status s = check_opts(opts)) return s;
     if (t->desc.dtype != PO_F32) return fail(PO_ERR_UNSUPPORTED, "gradients need float32 leaves");
+    if (po_view_opts(kopts(t, opts), nullptr))
+        return fail(PO_ERR_UNSUPPORTED, "gradients of renders with sh_off or a slicing plane are not provided");
     if (n < 0) return fail(PO_ERR_INVALID, "n = %lld < 0", (long long)n);
     if (n == 0) return ok();
     if (n > (1ll << 40)) return fail(PO_ERR_INVALID, "n = %lld too large", (long long)n);
@@ -486,14 +527,19 @@ po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream) {
                         tiles_of(&J.cam));
     }
     // group jobs by kernel variant, one launch per group, in order of first appearance
+    auto variant = [&](int q) {
+        const po_job& J = jobs[q];
+        const bool view = po_view_opts(kopts(J.tree, &J.opts), (J.opts.flags & PO_OUT_AUX) ? J.d_aux : nullptr);
+        return 2 * po_plan_id(J.tree) + (view ? 1 : 0);
+    };
     bool done[PO_BATCH_MAX_JOBS] = {false};
     for (int i = 0; i < n_jobs; ++i) {
         if (done[i]) continue;
-        const int plan = po_plan_id(jobs[i].tree);
+        const int plan = variant(i);
         KJob kj[PO_BATCH_MAX_JOBS];
         int nj = 0, blocks = 0;
         for (int q = i; q < n_jobs; ++q) {
-            if (done[q] || po_plan_id(jobs[q].tree) != plan) continue;
+            if (done[q] || variant(q) != plan) continue;
             done[q] = true;
             const po_job& J = jobs[q];
             const int nt = J.tile_end - J.tile_begin;
@@ -511,9 +557,25 @@ po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream) {
             blocks += 4 * nt;
         }
         if (nj == 0) continue;
-        hipError_t e = po_launch_camera_jobs(jobs[i].tree, nj, kj, blocks, (hipStream_t)stream);
+        hipError_t e = po_launch_camera_jobs(jobs[i].tree, nj, kj, blocks, (plan & 1) != 0, (hipStream_t)stream);
         if (e != hipSuccess) return device_fail(e, "render_batch launch");
     }
+    return ok();
+}
+
+po_status po_leaf_weights(const po_tree* t, const po_camera* cam, const po_render_opts* opts, int32_t mode,
+                          float* d_weight, float* d_alpha, void* stream) {
+    if (!t) return fail(PO_ERR_INVALID, "tree is NULL");
+    if (po_status s = check_camera(cam)) return s;
+    if (po_status s = check_opts(opts)) return s;
+    if (mode != PO_WEIGHT_ALPHA && mode != PO_WEIGHT_CONTRIB) return fail(PO_ERR_INVALID, "unknown weight mode %d", mode);
+    if (opts->flags != 0) return fail(PO_ERR_INVALID, "filter renders take no output flags");
+    const KOpts k = kopts(t, opts);
+    if (po_view_opts(k, nullptr))
+        return fail(PO_ERR_UNSUPPORTED, "filter renders take no sh_off or slicing plane");
+    if (!d_weight && t->n_leaves > 0) return fail(PO_ERR_INVALID, "weight array is NULL");
+    hipError_t e = po_launch_leaf_weights(t, kcam(cam), k, mode, d_weight, d_alpha, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "leaf_weights launch");
     return ok();
 }
 

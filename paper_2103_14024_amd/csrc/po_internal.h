@@ -27,7 +27,16 @@ struct KOpts {
     float stop_T;
     int32_t max_steps;
     uint32_t flags;
+    uint32_t sh_off;        // viewer: SH basis functions left out
+    float clip[4];          // viewer: slicing half-space n.x + w >= 0 (all zero: none)
 };
+
+// True when a render needs the viewer kernels (aux outputs with depth, SH
+// subsets or a slicing plane); the plain kernels serve every other call.
+inline bool po_view_opts(const KOpts& k, const float* aux) {
+    return aux != nullptr || k.sh_off != 0u || k.clip[0] != 0.0f || k.clip[1] != 0.0f || k.clip[2] != 0.0f ||
+           k.clip[3] != 0.0f;
+}
 
 struct KCam {
     float c2w[12];
@@ -67,10 +76,14 @@ hipError_t po_launch_backward(const po_tree* t, int64_t n, const float* o, const
                               const KOpts& op, const float* rgb_fwd, const float* grad_rgb,
                               float* grad_sigma, float* grad_sh, hipStream_t s);
 // Renders camera jobs that all share dtype, K and vec_bytes (at most
-// PO_BATCH_MAX_JOBS); n_blocks counts workgroups, four per 16x16 tile.
-hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks,
+// PO_BATCH_MAX_JOBS) and the same po_view_opts; n_blocks counts workgroups,
+// four per 16x16 tile.
+hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, bool view,
                                  hipStream_t s);
 hipError_t po_launch_camera_rays(const KCam& cam, float* o, float* d, hipStream_t s);
+// Visibility filter: mode 0 alpha, 1 contribution; weight[n_leaves] raised in place, alpha[H*W] or nullptr.
+hipError_t po_launch_leaf_weights(const po_tree* t, const KCam& cam, const KOpts& op, int mode, float* weight,
+                                  float* alpha, hipStream_t s);
 hipError_t po_launch_mse_grad(int64_t n, const float* rgb, const float* target, float scale, float* grad,
                               float* sq_sum, hipStream_t s);
 hipError_t po_launch_sgd(int64_t n, float* param, float* grad, float lr, bool zero_grad, hipStream_t s);

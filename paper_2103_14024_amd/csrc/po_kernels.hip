@@ -35,7 +35,7 @@ namespace {
 constexpr int kBlock = 64;
 
 // ---------------------------------------------------------------------------
-// Real SH basis up to degree 3 at a unit direction (App. B.1), written as
+// Real SH basis up to degree 4 at a unit direction (App. B.1), written as
 // polynomials in x, y, z.  Index l*l + l + m.  Sign convention: P_l^m carries
 // the Condon-Shortley phase, which cancels the (-1)^m of the real
 // combination, so every coefficient below is positive.
@@ -63,6 +63,18 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float (&Y)[K
             Y[13] = 0.4570457994644658f * (x * (5.0f * zz - 1.0f));
             Y[14] = 1.445305721320277f * (z * (xx - yy));           // sqrt(105/pi)/4
             Y[15] = 0.5900435899266435f * (x * (xx - 3.0f * yy));
+            if constexpr (K > 16) {
+                const float z7a = 7.0f * zz - 1.0f, z7b = 7.0f * zz - 3.0f;
+                Y[16] = 2.5033429417967046f * (x * y * (xx - yy));          // 3 sqrt(35/pi)/4
+                Y[17] = 1.7701307697799304f * (y * z * (3.0f * xx - yy));   // 3 sqrt(35/(2 pi))/4
+                Y[18] = 0.9461746957575601f * (x * y * z7a);                // 3 sqrt(5/pi)/4
+                Y[19] = 0.6690465435572892f * (y * z * z7b);                // 3 sqrt(5/(2 pi))/4
+                Y[20] = 0.10578554691520431f * ((35.0f * zz - 30.0f) * zz + 3.0f);  // 3/(16 sqrt(pi))
+                Y[21] = 0.6690465435572892f * (x * z * z7b);
+                Y[22] = 0.47308734787878004f * ((xx - yy) * z7a);           // 3 sqrt(5/pi)/8
+                Y[23] = 1.7701307697799304f * (x * z * (xx - 3.0f * yy));
+                Y[24] = 0.6258357354491761f * (xx * (xx - 3.0f * yy) - yy * (3.0f * xx - yy));  // 3 sqrt(35/pi)/16
+            }
         }
     }
 }
@@ -191,9 +203,12 @@ struct Ray {
     float dn[3];   // unit direction, world (SH argument)
     int c[3];      // finest-level coordinates of the current cell
     double s;      // current parameter
+    double s_end;  // end of the rendered part (slicing plane), else 1e300
 };
 
-__device__ __forceinline__ bool ray_setup(const KTree& tr, const double (&o)[3], const double (&d)[3], Ray& r) {
+// The walk covers the parameters s in [max(s_lo, 0), s_hi] inside the box.
+__device__ __forceinline__ bool ray_setup(const KTree& tr, const double (&o)[3], const double (&d)[3], Ray& r,
+                                          double s_lo = 0.0, double s_hi = 1e300) {
     const double len2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     if (!(len2 > 0.0) || !(len2 < 1e300)) return false;
     r.len = sqrt(len2);
@@ -201,7 +216,7 @@ __device__ __forceinline__ bool ray_setup(const KTree& tr, const double (&o)[3],
 #pragma unroll
     for (int k = 0; k < 3; ++k) r.dn[k] = (float)(d[k] * il);
     const double N = (double)(1 << tr.depth);
-    double s0 = 0.0, s1 = 1e300;
+    double s0 = fmax(s_lo, 0.0), s1 = s_hi;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         r.og[k] = (o[k] - tr.lo[k]) * tr.scale;
@@ -225,7 +240,22 @@ __device__ __forceinline__ bool ray_setup(const KTree& tr, const double (&o)[3],
         r.c[k] = (int)fmin(fmax(floor(p), 0.0), N - 1.0);
     }
     r.s = s0;
+    r.s_end = s_hi;
     return true;
+}
+
+// Parameter range [s_lo, s_hi] of the ray o + s d inside the slicing
+// half-space n.x + w >= 0 of the viewer (Sec. 5.5); a ray parallel to the
+// plane and outside it gets an empty range.  An all-zero plane keeps the
+// whole ray.
+__device__ __forceinline__ void clip_range(const KOpts& op, const double (&o)[3], const double (&d)[3],
+                                           double& s_lo, double& s_hi) {
+    const double nx = op.clip[0], ny = op.clip[1], nz = op.clip[2], w = op.clip[3];
+    const double p0 = nx * o[0] + ny * o[1] + nz * o[2] + w;
+    const double pd = nx * d[0] + ny * d[1] + nz * d[2];
+    const double t = -p0 / pd;  // crossing (unused when pd == 0)
+    s_lo = pd > 0.0 ? t : ((pd == 0.0) & (p0 < 0.0) ? 1e300 : 0.0);
+    s_hi = pd < 0.0 ? t : 1e300;
 }
 
 // Child slot of cell c below a node of level L (bits D-1-L of the coordinates).
@@ -235,10 +265,12 @@ __device__ __forceinline__ uint32_t child_slot(const int (&c)[3], int D, int L) 
 }
 
 // Walks the segments of a ray.  Data leaves crossed over a positive length
-// go through a two-stage sampler: smp.issue(leaf, delta) starts the loads of
-// the leaf's density and SH record (leaf -1: a lane without a sample, which
-// loads nothing), and smp.consume() shades and composites the sample one step
-// later and returns true to stop the walk.  The samples, their order and the
+// go through a two-stage sampler: smp.issue(leaf, delta, t) starts the loads
+// of the leaf's density and SH record (leaf -1: a lane without a sample,
+// which loads nothing; t is the segment's start distance from the origin),
+// and smp.consume() shades and composites the sample one step later and
+// returns true to stop the walk; smp.flush() then runs with every lane still
+// walking.  A sampler with kClip set also ends the walk at r.s_end.  The samples, their order and the
 // stop point are those of the plain front-to-back walk.  Returns the number
 // of cells visited.
 //
@@ -270,7 +302,7 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
     int e = __builtin_amdgcn_raw_buffer_load_b32(child, child_slot(r.c, D, 0) << 2, 0, 0);
     // an empty gather, so that every path into the loop has the same loads in
     // flight behind the entry (the compiler then waits for the entry alone)
-    smp.issue(-1, 0.0f);
+    smp.issue(-1, 0.0f, 0.0f);
     while (true) {
         // finish the descent: e is the entry of the level-(L+1) cell holding c
         ++L;
@@ -307,8 +339,10 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
             pos[k] = r.dg[k] > 0.0;
             sk[k] = ((double)(lo[k] + (pos[k] ? csz : 0)) - r.og[k]) * r.inv[k];
         }
-        const double se = fmax(fmin(fmin(sk[0], sk[1]), sk[2]), r.s);
+        double se = fmax(fmin(fmin(sk[0], sk[1]), sk[2]), r.s);
+        if constexpr (Sampler::kClip) se = fmin(se, r.s_end);
         const float delta = (float)((se - r.s) * r.len);
+        const float t_in = (float)(r.s * r.len);
         ++steps;
         // next cell: axes whose face is reached step to the neighbouring cell;
         // the others take the finest cell of the exit point, kept inside the
@@ -325,6 +359,7 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
             nc[k] = cross ? stepped : kept;
             out |= cross & ((stepped < 0) | (stepped >= N));
         }
+        if constexpr (Sampler::kClip) out |= se >= r.s_end;
         r.s = se;
         const bool capped = !out & (steps >= max_steps);
         bad |= capped;
@@ -350,15 +385,17 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
             pending = false;
             stop = smp.consume();
         }
+        smp.flush();
         // start this cell's gather; lanes without a sample load nothing.  The
         // walk ends only at the bottom of the body, so every path back to the
         // top has issued the same loads.
         const bool take = !stop & (leaf >= 0) & (delta > 0.0f);
-        smp.issue(take ? leaf : -1, delta);
+        smp.issue(take ? leaf : -1, delta, t_in);
         pending = take;
         if (last | stop) break;
     }
     if (pending) smp.consume();
+    smp.flush();
     // a lane that met a malformed entry or the step cap is counted once
     if (bad) atomicAdd(&g_po_errors, 1ull);
     return steps;
@@ -373,26 +410,32 @@ __device__ __forceinline__ float dot_channel(const uint32_t (&w)[NW], int base, 
 }
 
 // Forward shading and compositing of the samples of one ray (Sec. 3
-// eqn:quad, Sec. 4.1 colour, App. B.3 clamp of the raw density).
-template <typename T, int K, int VEC, int NL>
+// eqn:quad, Sec. 4.1 colour, App. B.3 clamp of the raw density).  VIEW adds
+// the viewer outputs of Sec. 5.5: the expected termination distance and the
+// end of the walk at a slicing plane.
+template <typename T, int K, int VEC, int NL, bool VIEW>
 struct FwdSampler {
     static constexpr int NW = Words<T, NL>::N;
+    static constexpr bool kClip = VIEW;
     __amdgpu_buffer_rsrc_t sig, shb;
     uint32_t sig_end, sh_end, rec_bytes;
     float stopT;
     float Y[K];
     float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, Tl = 1.0f;
+    float dep = 0.0f;
     int ns = 0;
     // in flight
-    float raw, delta;
+    float raw, delta, ta;
     uint32_t w[NW];
 
     // leaf < 0: no sample; the out-of-range offsets load zeros without memory traffic
-    __device__ __forceinline__ void issue(int leaf, float d) {
+    __device__ __forceinline__ void issue(int leaf, float d, float t_in) {
         raw = sigma_buf(sig, leaf < 0 ? sig_end : (uint32_t)leaf * (uint32_t)sizeof(T), (T*)nullptr);
         load_words_buf<T, NL, VEC>(shb, leaf < 0 ? sh_end : (uint32_t)leaf * rec_bytes, w);
         delta = d;
+        if constexpr (VIEW) ta = t_in;
     }
+    __device__ __forceinline__ void flush() {}
     __device__ __forceinline__ bool consume() {
         ++ns;
         const float s = fmaxf(raw, 0.0f);
@@ -402,23 +445,39 @@ struct FwdSampler {
         c0 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, 0, Y)), c0);
         c1 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, K, Y)), c1);
         c2 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, 2 * K, Y)), c2);
+        if constexpr (VIEW) {
+            // integral of t sigma T(t) over the segment [ta, ta + delta]:
+            // Tl (ta alpha + delta f), f = alpha / tau - e^-tau, from its
+            // series below tau = 0.05 (alpha / tau cancels there)
+            const float tau = s * delta;
+            const float al = 1.0f - ex;
+            const float f = tau < 0.05f
+                                ? tau * (0.5f - tau * (1.0f / 3.0f - tau * (0.125f - tau * (1.0f / 30.0f - tau * (1.0f / 144.0f)))))
+                                : al / tau - ex;
+            dep = fmaf(Tl, fmaf(ta, al, delta * f), dep);
+        }
         Tl = Tl * ex;
         return Tl < stopT;
     }
 };
 
-// Renders one ray: colour (background included), final T, samples, steps.
-template <typename T, int K, int VEC, int NL>
+// Renders one ray: colour (background included), final T, samples, steps
+// and, with VIEW, the expected termination distance, SH subsets and the
+// slicing plane.
+template <typename T, int K, int VEC, int NL, bool VIEW>
 __device__ __forceinline__ void render_one(const KTree& tr, const KOpts& op, const double (&o)[3],
                                            const double (&d)[3], int* __restrict__ stk, float (&C)[3], float& Tr,
-                                           int& ns, int& steps) {
+                                           int& ns, int& steps, float& dep) {
     C[0] = C[1] = C[2] = 0.0f;
     Tr = 1.0f;
     ns = 0;
     steps = 0;
+    dep = 0.0f;
     Ray r;
-    if (ray_setup(tr, o, d, r)) {
-        FwdSampler<T, K, VEC, NL> smp;
+    double s_lo = 0.0, s_hi = 1e300;
+    if constexpr (VIEW) clip_range(op, o, d, s_lo, s_hi);
+    if (ray_setup(tr, o, d, r, s_lo, s_hi)) {
+        FwdSampler<T, K, VEC, NL, VIEW> smp;
         smp.sig = raw_rsrc(tr.sigma, tr.sigma_bytes);
         smp.shb = raw_rsrc(tr.sh, tr.sh_bytes);
         smp.sig_end = tr.sigma_bytes;
@@ -426,12 +485,18 @@ __device__ __forceinline__ void render_one(const KTree& tr, const KOpts& op, con
         smp.rec_bytes = (uint32_t)tr.stride * (uint32_t)sizeof(T);
         smp.stopT = op.stop_T;
         sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], smp.Y);
+        if constexpr (VIEW) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if ((op.sh_off >> k) & 1u) smp.Y[k] = 0.0f;
+        }
         steps = march(tr, r, op.max_steps, stk, smp);
         C[0] = smp.c0;
         C[1] = smp.c1;
         C[2] = smp.c2;
         Tr = smp.Tl;
         ns = smp.ns;
+        dep = smp.dep;
     }
     C[0] = fmaf(Tr, op.bg[0], C[0]);
     C[1] = fmaf(Tr, op.bg[1], C[1]);
@@ -448,7 +513,7 @@ __device__ __forceinline__ int64_t xcd_swizzle(int64_t b, int64_t n_logical) {
     return l < n_logical ? l : -1;
 }
 
-template <typename T, int K, int VEC, int NL>
+template <typename T, int K, int VEC, int NL, bool VIEW>
 __global__ __launch_bounds__(kBlock) void k_render_rays(KTree tr, int64_t n, int64_t n_blocks,
                                                         const float* __restrict__ o,
                                                         const float* __restrict__ d, KOpts op,
@@ -459,17 +524,20 @@ __global__ __launch_bounds__(kBlock) void k_render_rays(KTree tr, int64_t n, int
     if (i >= n) return;
     const double ro[3] = {(double)o[3 * i], (double)o[3 * i + 1], (double)o[3 * i + 2]};
     const double rd[3] = {(double)d[3 * i], (double)d[3 * i + 1], (double)d[3 * i + 2]};
-    float C[3], Tr;
+    float C[3], Tr, dep;
     int ns, steps;
     extern __shared__ int po_stack[];
-    render_one<T, K, VEC, NL>(tr, op, ro, rd, po_stack + threadIdx.x, C, Tr, ns, steps);
+    render_one<T, K, VEC, NL, VIEW>(tr, op, ro, rd, po_stack + threadIdx.x, C, Tr, ns, steps, dep);
     rgb[3 * i + 0] = C[0];
     rgb[3 * i + 1] = C[1];
     rgb[3 * i + 2] = C[2];
-    if (aux) {
-        aux[3 * i + 0] = Tr;
-        aux[3 * i + 1] = (float)ns;
-        aux[3 * i + 2] = (float)steps;
+    if constexpr (VIEW) {
+        if (aux) {
+            aux[4 * i + 0] = Tr;
+            aux[4 * i + 1] = (float)ns;
+            aux[4 * i + 2] = (float)steps;
+            aux[4 * i + 3] = dep;
+        }
     }
 }
 
@@ -506,10 +574,12 @@ struct KBatch {
     int32_t n_jobs;
     int32_t n_blocks;
 };
+// passed by value as the kernel argument block, limited to 4 KiB
+static_assert(sizeof(KBatch<PO_BATCH_MAX_JOBS>) <= 4096, "batched kernel arguments exceed 4 KiB");
 
 // Camera jobs: a 16x16 tile is rendered by four single-wave workgroups, one
 // per 8x8 quadrant; lane l takes the pixel (l & 7, l >> 3) of its quadrant.
-template <typename T, int K, int VEC, int NL, int MAXJ>
+template <typename T, int K, int VEC, int NL, int MAXJ, bool VIEW>
 __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
     const int64_t b = xcd_swizzle(blockIdx.x, B.n_blocks);
     if (b < 0) return;
@@ -528,18 +598,21 @@ __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
     if (px >= J.cam.W || py >= J.cam.H) return;
     double ro[3], rd[3];
     pixel_ray(J.cam, px, py, ro, rd);
-    float C[3], Tr;
+    float C[3], Tr, dep;
     int ns, steps;
     extern __shared__ int po_stack[];
-    render_one<T, K, VEC, NL>(J.tr, J.op, ro, rd, po_stack + threadIdx.x, C, Tr, ns, steps);
+    render_one<T, K, VEC, NL, VIEW>(J.tr, J.op, ro, rd, po_stack + threadIdx.x, C, Tr, ns, steps, dep);
     const size_t p = (size_t)py * J.cam.W + px;
     J.rgb[3 * p + 0] = C[0];
     J.rgb[3 * p + 1] = C[1];
     J.rgb[3 * p + 2] = C[2];
-    if (J.aux) {
-        J.aux[3 * p + 0] = Tr;
-        J.aux[3 * p + 1] = (float)ns;
-        J.aux[3 * p + 2] = (float)steps;
+    if constexpr (VIEW) {
+        if (J.aux) {
+            J.aux[4 * p + 0] = Tr;
+            J.aux[4 * p + 1] = (float)ns;
+            J.aux[4 * p + 2] = (float)steps;
+            J.aux[4 * p + 3] = dep;
+        }
     }
 }
 
@@ -551,6 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
 template <int K, int VEC, int NL>
 struct BwdSampler {
     static constexpr int NW = Words<float, NL>::N;
+    static constexpr bool kClip = false;
     __amdgpu_buffer_rsrc_t sig, shb;
     uint32_t sig_end, sh_end, rec_bytes;
     int stride;
@@ -565,12 +639,13 @@ struct BwdSampler {
     float raw, delta;
     uint32_t w[NW];
 
-    __device__ __forceinline__ void issue(int l, float d) {
+    __device__ __forceinline__ void issue(int l, float d, float) {
         leaf = l;
         raw = sigma_buf(sig, l < 0 ? sig_end : (uint32_t)l * 4u, (float*)nullptr);
         load_words_buf<float, NL, VEC>(shb, l < 0 ? sh_end : (uint32_t)l * rec_bytes, w);
         delta = d;
     }
+    __device__ __forceinline__ void flush() {}
     __device__ __forceinline__ bool consume() {
         const float s = fmaxf(raw, 0.0f);
         if (!(s > 0.0f)) return false;  // no density: zero weight, and dC/dsigma is masked
@@ -640,6 +715,72 @@ __global__ __launch_bounds__(kBlock) void k_backward(KTree tr, int64_t n, int64_
     march(tr, r, op.max_steps, po_stack + threadIdx.x, smp);
 }
 
+// Visibility filter of the conversion (Sec. 4.2, "Filtering"): alpha
+// renders of a camera that raise every leaf's weight to the largest weight
+// of a segment in it, MODE 0 the segment's alpha 1 - exp(-sigma delta),
+// MODE 1 its contribution T alpha.  Only the densities are gathered.  The
+// weights are non-negative floats, whose bit patterns order like unsigned
+// integers, so the maximum is an integer atomic.
+template <typename T, int MODE>
+struct WeightSampler {
+    static constexpr bool kClip = false;
+    __amdgpu_buffer_rsrc_t sig;
+    uint32_t sig_end;
+    float stopT;
+    unsigned* wt;
+    float Tl = 1.0f;
+    // in flight
+    int leaf;
+    float raw, delta;
+
+    __device__ __forceinline__ void issue(int l, float d, float) {
+        leaf = l;
+        raw = sigma_buf(sig, l < 0 ? sig_end : (uint32_t)l * (uint32_t)sizeof(T), (T*)nullptr);
+        delta = d;
+    }
+    __device__ __forceinline__ void flush() {}
+    __device__ __forceinline__ bool consume() {
+        const float s = fmaxf(raw, 0.0f);
+        if (!(s > 0.0f)) return false;
+        const float ex = __expf(-(s * delta));
+        const float al = 1.0f - ex;
+        const float w = MODE ? Tl * al : al;
+        if (w > 0.0f) atomicMax(wt + leaf, __float_as_uint(w));
+        Tl = Tl * ex;
+        return Tl < stopT;
+    }
+};
+
+// One camera, 16x16 tiles of four 8x8 single-wave workgroups as in
+// k_render_camera; alpha (or nullptr) receives 1 - T per pixel.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_leaf_weights(KTree tr, KCam cam, KOpts op, int n_blocks,
+                                                         unsigned* __restrict__ wt, float* __restrict__ alpha) {
+    const int64_t b = xcd_swizzle(blockIdx.x, n_blocks);
+    if (b < 0) return;
+    const int tiles_x = (cam.W + 15) / 16;
+    const int tile = (int)(b >> 2), quad = (int)(b & 3);
+    const int lane = threadIdx.x;
+    const int px = (tile % tiles_x) * 16 + (quad & 1) * 8 + (lane & 7);
+    const int py = (tile / tiles_x) * 16 + (quad >> 1) * 8 + (lane >> 3);
+    if (px >= cam.W || py >= cam.H) return;
+    double ro[3], rd[3];
+    pixel_ray(cam, px, py, ro, rd);
+    float Tr = 1.0f;
+    Ray r;
+    if (ray_setup(tr, ro, rd, r)) {
+        WeightSampler<T, MODE> smp;
+        smp.sig = raw_rsrc(tr.sigma, tr.sigma_bytes);
+        smp.sig_end = tr.sigma_bytes;
+        smp.stopT = op.stop_T;
+        smp.wt = wt;
+        extern __shared__ int po_stack[];
+        march(tr, r, op.max_steps, po_stack + threadIdx.x, smp);
+        Tr = smp.Tl;
+    }
+    if (alpha) alpha[(size_t)py * cam.W + px] = 1.0f - Tr;
+}
+
 // Loss gradient of the NeRF loss (Sec. 3, eqn:nerfloss) for one batch: one
 // thread per ray; squared errors are summed within the wave and added once
 // per wave.
@@ -698,17 +839,28 @@ hipError_t rays_t(const po_tree* t, int64_t n, const float* o, const float* d, c
     using P = Plan<T, K>;
     const int64_t nb = (n + kBlock - 1) / kBlock;
     dim3 grid((unsigned)grid_for(nb)), block(kBlock);
-    if (use_fast<T, K>(t))
-        hipLaunchKernelGGL((k_render_rays<T, K, P::FAST_VEC, P::FAST_NL>), grid, block, stack_bytes(t->kt.depth),
-                           s, t->kt, n, nb, o, d, op, rgb, aux);
-    else
-        hipLaunchKernelGGL((k_render_rays<T, K, 4, P::GEN_NL>), grid, block, stack_bytes(t->kt.depth), s, t->kt,
-                           n, nb, o, d, op, rgb, aux);
+    const size_t lds = stack_bytes(t->kt.depth);
+    const bool fast = use_fast<T, K>(t);
+    if (po_view_opts(op, aux)) {
+        if (fast)
+            hipLaunchKernelGGL((k_render_rays<T, K, P::FAST_VEC, P::FAST_NL, true>), grid, block, lds, s, t->kt, n,
+                               nb, o, d, op, rgb, aux);
+        else
+            hipLaunchKernelGGL((k_render_rays<T, K, 4, P::GEN_NL, true>), grid, block, lds, s, t->kt, n, nb, o, d,
+                               op, rgb, aux);
+    } else {
+        if (fast)
+            hipLaunchKernelGGL((k_render_rays<T, K, P::FAST_VEC, P::FAST_NL, false>), grid, block, lds, s, t->kt, n,
+                               nb, o, d, op, rgb, nullptr);
+        else
+            hipLaunchKernelGGL((k_render_rays<T, K, 4, P::GEN_NL, false>), grid, block, lds, s, t->kt, n, nb, o, d,
+                               op, rgb, nullptr);
+    }
     return hipGetLastError();
 }
 
 template <typename T, int K, int MAXJ>
-hipError_t camera_t(const po_tree* t, int n_jobs, KJob* jobs, int n_blocks, hipStream_t s) {
+hipError_t camera_t(const po_tree* t, int n_jobs, KJob* jobs, int n_blocks, bool view, hipStream_t s) {
     using P = Plan<T, K>;
     KBatch<MAXJ> B;
     for (int j = 0; j < n_jobs; ++j) B.job[j] = jobs[j];
@@ -718,11 +870,19 @@ hipError_t camera_t(const po_tree* t, int n_jobs, KJob* jobs, int n_blocks, hipS
     int depth = 1;
     for (int j = 0; j < n_jobs; ++j) depth = max(depth, jobs[j].tr.depth);
     dim3 grid((unsigned)grid_for(n_blocks)), block(kBlock);
-    if (use_fast<T, K>(t))
-        hipLaunchKernelGGL((k_render_camera<T, K, P::FAST_VEC, P::FAST_NL, MAXJ>), grid, block, stack_bytes(depth),
-                           s, B);
-    else
-        hipLaunchKernelGGL((k_render_camera<T, K, 4, P::GEN_NL, MAXJ>), grid, block, stack_bytes(depth), s, B);
+    const size_t lds = stack_bytes(depth);
+    const bool fast = use_fast<T, K>(t);
+    if (view) {
+        if (fast)
+            hipLaunchKernelGGL((k_render_camera<T, K, P::FAST_VEC, P::FAST_NL, MAXJ, true>), grid, block, lds, s, B);
+        else
+            hipLaunchKernelGGL((k_render_camera<T, K, 4, P::GEN_NL, MAXJ, true>), grid, block, lds, s, B);
+    } else {
+        if (fast)
+            hipLaunchKernelGGL((k_render_camera<T, K, P::FAST_VEC, P::FAST_NL, MAXJ, false>), grid, block, lds, s, B);
+        else
+            hipLaunchKernelGGL((k_render_camera<T, K, 4, P::GEN_NL, MAXJ, false>), grid, block, lds, s, B);
+    }
     return hipGetLastError();
 }
 
@@ -749,6 +909,7 @@ hipError_t backward_t(const po_tree* t, int64_t n, const float* o, const float* 
         case 4: { constexpr int KK = 4; return EXPR; }   \
         case 9: { constexpr int KK = 9; return EXPR; }   \
         case 16: { constexpr int KK = 16; return EXPR; } \
+        case 25: { constexpr int KK = 25; return EXPR; } \
         default: return hipErrorInvalidValue;        \
     }
 
@@ -761,24 +922,45 @@ hipError_t po_launch_rays(const po_tree* t, int64_t n, const float* o, const flo
     }
 }
 
-hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, hipStream_t s) {
+hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, bool view,
+                                 hipStream_t s) {
     if (n_jobs == 1) {
         if (first->desc.dtype == PO_F32) {
-            PO_DISPATCH_K(first->K, (camera_t<float, KK, 1>(first, n_jobs, jobs, n_blocks, s)));
+            PO_DISPATCH_K(first->K, (camera_t<float, KK, 1>(first, n_jobs, jobs, n_blocks, view, s)));
         } else {
-            PO_DISPATCH_K(first->K, (camera_t<__half, KK, 1>(first, n_jobs, jobs, n_blocks, s)));
+            PO_DISPATCH_K(first->K, (camera_t<__half, KK, 1>(first, n_jobs, jobs, n_blocks, view, s)));
         }
     }
     if (first->desc.dtype == PO_F32) {
-        PO_DISPATCH_K(first->K, (camera_t<float, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, s)));
+        PO_DISPATCH_K(first->K, (camera_t<float, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, view, s)));
     } else {
-        PO_DISPATCH_K(first->K, (camera_t<__half, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, s)));
+        PO_DISPATCH_K(first->K, (camera_t<__half, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, view, s)));
     }
 }
 
 hipError_t po_launch_backward(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
                               const float* rgb_fwd, const float* grad, float* gsig, float* gsh, hipStream_t s) {
     PO_DISPATCH_K(t->K, (backward_t<KK>(t, n, o, d, op, rgb_fwd, grad, gsig, gsh, s)));
+}
+
+hipError_t po_launch_leaf_weights(const po_tree* t, const KCam& cam, const KOpts& op, int mode, float* weight,
+                                  float* alpha, hipStream_t s) {
+    const int n_blocks = 4 * ((cam.W + 15) / 16) * ((cam.H + 15) / 16);
+    dim3 grid((unsigned)grid_for(n_blocks)), block(kBlock);
+    const size_t lds = stack_bytes(t->kt.depth);
+    unsigned* wt = reinterpret_cast<unsigned*>(weight);
+    if (t->desc.dtype == PO_F32) {
+        if (mode == 0)
+            hipLaunchKernelGGL((k_leaf_weights<float, 0>), grid, block, lds, s, t->kt, cam, op, n_blocks, wt, alpha);
+        else
+            hipLaunchKernelGGL((k_leaf_weights<float, 1>), grid, block, lds, s, t->kt, cam, op, n_blocks, wt, alpha);
+    } else {
+        if (mode == 0)
+            hipLaunchKernelGGL((k_leaf_weights<__half, 0>), grid, block, lds, s, t->kt, cam, op, n_blocks, wt, alpha);
+        else
+            hipLaunchKernelGGL((k_leaf_weights<__half, 1>), grid, block, lds, s, t->kt, cam, op, n_blocks, wt, alpha);
+    }
+    return hipGetLastError();
 }
 
 hipError_t po_launch_camera_rays(const KCam& cam, float* o, float* d, hipStream_t s) {

@@ -16,13 +16,28 @@ def _torch():
     return torch
 
 
-def make_opts(bg=(1.0, 1.0, 1.0), stop_T=1e-4, max_steps=0, aux=False) -> L.po_render_opts:
+# columns of the aux output: final transmittance (1 - alpha), data samples,
+# traversal steps, expected termination distance (depth map)
+AUX_T, AUX_SAMPLES, AUX_STEPS, AUX_DEPTH = 0, 1, 2, 3
+AUX_WIDTH = 4
+
+
+def make_opts(bg=(1.0, 1.0, 1.0), stop_T=1e-4, max_steps=0, aux=False, sh_off=0, clip=None) -> L.po_render_opts:
+    """Render options.  sh_off: bit k leaves out SH basis function k; clip:
+    slicing plane (nx, ny, nz, w), only n.x + w >= 0 is rendered."""
     o = L.po_render_opts()
     for k in range(3):
         o.bg[k] = float(bg[k])
     o.stop_T = float(stop_T)
     o.max_steps = int(max_steps)
     o.flags = L.PO_OUT_AUX if aux else 0
+    o.sh_off = int(sh_off) & 0xFFFFFFFF
+    if clip is not None:
+        c = [float(v) for v in clip]
+        if len(c) != 4:
+            raise ValueError("clip must hold 4 values (nx, ny, nz, w)")
+        for k in range(4):
+            o.clip[k] = c[k]
     return o
 
 
@@ -30,6 +45,14 @@ def _stream_ptr(stream=None):
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _out(t, shape, name):
+    """A caller-supplied output must be a contiguous float32 device tensor of the given shape."""
+    torch = _torch()
+    if not (t.is_cuda and t.dtype == torch.float32 and tuple(t.shape) == tuple(shape) and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 device tensor of shape {tuple(shape)}")
+    return t
 
 
 def _rays3(t, name):
@@ -64,34 +87,39 @@ class Camera:
 
 
 def render_rays(tree, origins, dirs, bg=(1.0, 1.0, 1.0), stop_T=1e-4, aux=False, max_steps=0, out=None,
-                aux_out=None, stream=None):
-    """Colours (n, 3) of rays (origins, dirs: float32 (n, 3) device tensors)."""
+                aux_out=None, stream=None, sh_off=0, clip=None):
+    """Colours (n, 3) of rays (origins, dirs: float32 (n, 3) device tensors);
+    with aux also the (n, 4) columns AUX_T, AUX_SAMPLES, AUX_STEPS, AUX_DEPTH."""
     torch = _torch()
     _rays3(origins, "origins")
     _rays3(dirs, "dirs")
     n = origins.shape[0]
     if dirs.shape[0] != n:
         raise ValueError("origins and dirs differ in length")
-    rgb = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=origins.device)
+    rgb = _out(out, (n, 3), "out") if out is not None else torch.empty((n, 3), dtype=torch.float32,
+                                                                       device=origins.device)
     a = None
     if aux:
-        a = aux_out if aux_out is not None else torch.empty((n, 3), dtype=torch.float32, device=origins.device)
-    opts = make_opts(bg, stop_T, max_steps, aux)
+        a = _out(aux_out, (n, AUX_WIDTH), "aux_out") if aux_out is not None else torch.empty(
+            (n, AUX_WIDTH), dtype=torch.float32, device=origins.device)
+    opts = make_opts(bg, stop_T, max_steps, aux, sh_off, clip)
     L.call("po_render_rays", tree.handle, n, origins.data_ptr(), dirs.data_ptr(), ctypes.byref(opts),
            rgb.data_ptr(), a.data_ptr() if a is not None else None, _stream_ptr(stream))
     return (rgb, a) if aux else rgb
 
 
 def render_camera(tree, cam: Camera, bg=(1.0, 1.0, 1.0), stop_T=1e-4, aux=False, max_steps=0, out=None,
-                  aux_out=None, stream=None, device="cuda"):
-    """Image (H, W, 3) of a camera."""
+                  aux_out=None, stream=None, device="cuda", sh_off=0, clip=None):
+    """Image (H, W, 3) of a camera; with aux also (H, W, 4) aux columns."""
     torch = _torch()
     shape = (cam.height, cam.width, 3)
-    img = out if out is not None else torch.empty(shape, dtype=torch.float32, device=device)
+    img = _out(out, shape, "out") if out is not None else torch.empty(shape, dtype=torch.float32, device=device)
     a = None
     if aux:
-        a = aux_out if aux_out is not None else torch.empty(shape, dtype=torch.float32, device=device)
-    opts = make_opts(bg, stop_T, max_steps, aux)
+        ashape = (cam.height, cam.width, AUX_WIDTH)
+        a = _out(aux_out, ashape, "aux_out") if aux_out is not None else torch.empty(
+            ashape, dtype=torch.float32, device=device)
+    opts = make_opts(bg, stop_T, max_steps, aux, sh_off, clip)
     c = cam.to_c()
     L.call("po_render_camera", tree.handle, ctypes.byref(c), ctypes.byref(opts), img.data_ptr(),
            a.data_ptr() if a is not None else None, _stream_ptr(stream))
@@ -178,16 +206,21 @@ class Job:
     tile_end: int = -1     # -1: to the last tile
     bg: tuple = (1.0, 1.0, 1.0)
     stop_T: float = 1e-4
-    aux_out: object = None
+    aux_out: object = None  # (H, W, 4) float32 device tensor or None
+    sh_off: int = 0
+    clip: object = None
 
 
 def render_batch(jobs, stream=None) -> None:
     """Renders up to 16 camera jobs (any trees, any sizes, tile sub-ranges)."""
     arr = (L.po_job * max(1, len(jobs)))()
     for i, j in enumerate(jobs):
+        _out(j.out, (j.cam.height, j.cam.width, 3), "Job.out")
+        if j.aux_out is not None:
+            _out(j.aux_out, (j.cam.height, j.cam.width, AUX_WIDTH), "Job.aux_out")
         arr[i].tree = j.tree.handle.value
         arr[i].cam = j.cam.to_c()
-        arr[i].opts = make_opts(j.bg, j.stop_T, 0, j.aux_out is not None)
+        arr[i].opts = make_opts(j.bg, j.stop_T, 0, j.aux_out is not None, j.sh_off, j.clip)
         arr[i].d_rgb = j.out.data_ptr()
         arr[i].d_aux = j.aux_out.data_ptr() if j.aux_out is not None else None
         arr[i].tile_begin = int(j.tile_begin)

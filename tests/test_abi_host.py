@@ -178,6 +178,18 @@ def test_bind_and_argument_errors(lib):
     opts.max_steps = -1
     assert lib.po_render_rays(h, 5, fake, fake, ctypes.byref(opts), fake, None, None) == L.PO_ERR_INVALID
     opts.max_steps = 0
+    opts.clip[2] = float("nan")  # slicing plane must be finite
+    assert lib.po_render_rays(h, 5, fake, fake, ctypes.byref(opts), fake, None, None) == L.PO_ERR_INVALID
+    opts.clip[2] = 0.0
+    # viewer options have no gradient
+    for field, val in (("sh_off", 2), ("clip", 1.0)):
+        if field == "sh_off":
+            opts.sh_off = val
+        else:
+            opts.clip[3] = val
+        st = lib.po_render_rays_backward(h, 5, fake, fake, ctypes.byref(opts), fake, fake, fake, fake, None)
+        assert st == L.PO_ERR_UNSUPPORTED and b"slicing" in lib.po_last_error()
+        opts.sh_off, opts.clip[3] = 0, 0.0
     cam = L.po_camera()
     cam.width, cam.height, cam.fx, cam.fy = 0, 10, 1.0, 1.0
     assert lib.po_render_camera(h, ctypes.byref(cam), ctypes.byref(opts), fake, None, None) == L.PO_ERR_INVALID
@@ -227,3 +239,25 @@ def test_fp16_stride_must_be_dword_multiple(lib):
     assert lib.po_tree_bind(ctypes.byref(desc), 10, 0x1000, 20, 0x1000, 0x1000, ctypes.byref(h)) == L.PO_ERR_INVALID
     desc.sh_stride = 0  # 3K = 27 halves: not a multiple of 4 bytes
     assert lib.po_tree_bind(ctypes.byref(desc), 10, 0x1000, 20, 0x1000, 0x1000, ctypes.byref(h)) == L.PO_ERR_INVALID
+
+
+@pytest.mark.parametrize("seed,depth", [(0, 4), (3, 6)])
+def test_leaf_cells_recover_the_builder_input(lib, seed, depth):
+    cells = scenes.random_tree_cells(depth, seed)
+    child, perm = build_host(depth, 2, cells)
+    desc = make_desc(depth, 2)
+    n = len(cells)
+    out = np.empty((n, 4), np.int32)
+    ch = np.ascontiguousarray(child)
+    L.call("po_tree_leaf_cells", ctypes.byref(desc), ch.shape[0], ch.ctypes.data, n, out.ctypes.data)
+    # leaf j of the tree is the caller's cell perm[j]
+    np.testing.assert_array_equal(out, np.asarray(cells, np.int32)[perm])
+    # a leaf index no entry references is reported as (-1, -1, -1, -1)
+    out2 = np.empty((n + 1, 4), np.int32)
+    L.call("po_tree_leaf_cells", ctypes.byref(desc), ch.shape[0], ch.ctypes.data, n + 1, out2.ctypes.data)
+    assert np.all(out2[n] == -1) and np.array_equal(out2[:n], out)
+    # a malformed array is refused
+    bad = ch.copy()
+    bad[0, 0] = ch.shape[0] + 5
+    st = lib.po_tree_leaf_cells(ctypes.byref(desc), bad.shape[0], bad.ctypes.data, n, out.ctypes.data)
+    assert st == L.PO_ERR_TREE
