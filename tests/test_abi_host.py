@@ -223,7 +223,7 @@ def test_bind_and_argument_errors(lib):
     lib.po_tree_destroy(h)
 
 
-@pytest.mark.parametrize("field,value", [("depth", 0), ("depth", 16), ("sh_degree", 4), ("sh_degree", -1),
+@pytest.mark.parametrize("field,value", [("depth", 0), ("depth", 16), ("sh_degree", 5), ("sh_degree", -1),
                                          ("half_size", 0.0), ("dtype", 7), ("sh_stride", 5)])
 def test_bad_descriptions(lib, field, value):
     desc = make_desc(5, 2)
