@@ -167,6 +167,18 @@ po_status po_tree_validate(const po_tree_desc* desc, int64_t n_nodes, const int3
  * return PO_ERR_UNSUPPORTED.  Errors: PO_ERR_INVALID, PO_ERR_UNSUPPORTED. */
 po_status po_tree_bind(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child,
                        int64_t n_leaves, const void* d_sigma, const void* d_sh, po_tree** out);
+/* po_tree_bind_sg: as po_tree_bind, for a tree whose colour basis is
+ * K = (sh_degree+1)^2 spherical Gaussians instead of the SH (App. B.1, the
+ * SG-25 variant of the basis ablation, App. A): the colour of a leaf is
+ * sigmoid(sum_j k_j G_j(d)) with G_j(d) = exp(lambda_j (d . p_j / |p_j| -
+ * 1)).  d_lobes is a device array [K][4] = (p_x, p_y, p_z, lambda) of the
+ * lobes shared by all leaves, float32, 16-byte aligned, borrowed like the
+ * other arrays; every axis must be non-zero.  The leaf records keep the SH
+ * layout with K coefficients per channel.  Renders, gradients (with respect
+ * to the leaf values; the lobes are held fixed) and the filter all use the
+ * bound basis; sh_off then drops lobes.  Errors as for po_tree_bind. */
+po_status po_tree_bind_sg(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
+                          const void* d_sigma, const void* d_sh, const float* d_lobes, po_tree** out);
 po_status po_tree_destroy(po_tree* t);
 
 /* ------------------------------------------------------------------ render

@@ -359,8 +359,8 @@ po_status po_tree_leaf_cells(const po_tree_desc* desc, int64_t n_nodes, const in
     return ok();
 }
 
-po_status po_tree_bind(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
-                       const void* d_sigma, const void* d_sh, po_tree** out) {
+static po_status bind_impl(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
+                           const void* d_sigma, const void* d_sh, const float* d_lobes, po_tree** out) {
     if (po_status s = check_desc(desc)) return s;
     if (!out) return fail(PO_ERR_INVALID, "out is NULL");
     if (n_nodes < 1 || n_nodes >= (1ll << 31) / 8) return fail(PO_ERR_INVALID, "n_nodes %lld out of range", (long long)n_nodes);
@@ -401,6 +401,7 @@ po_status po_tree_bind(const po_tree_desc* desc, int64_t n_nodes, const int32_t*
     k.child = d_child;
     k.sigma = d_sigma;
     k.sh = d_sh;
+    k.lobes = d_lobes;
     k.n_nodes = (int32_t)n_nodes;
     k.n_leaves = (int32_t)n_leaves;
     k.stride = t->stride;
@@ -411,6 +412,18 @@ po_status po_tree_bind(const po_tree_desc* desc, int64_t n_nodes, const int32_t*
     k.scale = (double)(1 << desc->depth) / (2.0 * (double)desc->half_size);
     *out = t;
     return ok();
+}
+
+po_status po_tree_bind(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
+                       const void* d_sigma, const void* d_sh, po_tree** out) {
+    return bind_impl(desc, n_nodes, d_child, n_leaves, d_sigma, d_sh, nullptr, out);
+}
+
+po_status po_tree_bind_sg(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
+                          const void* d_sigma, const void* d_sh, const float* d_lobes, po_tree** out) {
+    if (!d_lobes) return fail(PO_ERR_INVALID, "lobe array is NULL");
+    if (((uintptr_t)d_lobes) % 16) return fail(PO_ERR_INVALID, "lobe array must be 16-byte aligned");
+    return bind_impl(desc, n_nodes, d_child, n_leaves, d_sigma, d_sh, d_lobes, out);
 }
 
 po_status po_tree_destroy(po_tree* t) {

@@ -12,6 +12,7 @@ struct KTree {
     const int32_t* child;   // [n_nodes][8]
     const void* sigma;      // [n_leaves] float or half
     const void* sh;         // [n_leaves][stride] float or half
+    const float* lobes;     // nullptr: SH colour basis; else [K][4] spherical-Gaussian lobes
     int32_t n_nodes;
     int32_t n_leaves;
     int32_t stride;         // elements per SH record

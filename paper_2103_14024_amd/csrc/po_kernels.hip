@@ -79,6 +79,30 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, float (&Y)[K
     }
 }
 
+// Spherical-Gaussian basis (App. B.1): G_j(d) = exp(lambda_j (d . p_j - 1))
+// for the tree's K lobes (axis p_j, normalised here, and bandwidth lambda_j),
+// in place of the SH of the same index.  The lobes are uniform across the
+// wave and read once per ray.
+template <int K>
+__device__ __forceinline__ void sg_basis(const float* __restrict__ lobes, float x, float y, float z,
+                                         float (&Y)[K]) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const float px = lobes[4 * j], py = lobes[4 * j + 1], pz = lobes[4 * j + 2], lam = lobes[4 * j + 3];
+        const float c = (x * px + y * py + z * pz) * rsqrtf(px * px + py * py + pz * pz);
+        Y[j] = __expf(lam * (c - 1.0f));
+    }
+}
+
+// Colour basis of a tree at the unit direction (x, y, z).
+template <int K>
+__device__ __forceinline__ void colour_basis(const KTree& tr, float x, float y, float z, float (&Y)[K]) {
+    if (tr.lobes)
+        sg_basis<K>(tr.lobes, x, y, z, Y);
+    else
+        sh_basis<K>(x, y, z, Y);
+}
+
 // Buffer resource for raw (byte-addressed) loads from one array: loads at
 // offsets outside [0, bytes) return 0 instead of faulting (gfx9 descriptor
 // word 3 = 0x00020000: raw buffer, 32-bit data format).
@@ -484,7 +508,7 @@ __device__ __forceinline__ void render_one(const KTree& tr, const KOpts& op, con
         smp.sh_end = tr.sh_bytes;
         smp.rec_bytes = (uint32_t)tr.stride * (uint32_t)sizeof(T);
         smp.stopT = op.stop_T;
-        sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], smp.Y);
+        colour_basis<K>(tr, r.dn[0], r.dn[1], r.dn[2], smp.Y);
         if constexpr (VIEW) {
 #pragma unroll
             for (int k = 0; k < K; ++k)
@@ -710,7 +734,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(KTree tr, int64_t n, int64_
     smp.stopT = op.stop_T;
     smp.gsig = gsig;
     smp.gsh = gsh;
-    sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], smp.Y);
+    colour_basis<K>(tr, r.dn[0], r.dn[1], r.dn[2], smp.Y);
     extern __shared__ int po_stack[];
     march(tr, r, op.max_steps, po_stack + threadIdx.x, smp);
 }

@@ -45,6 +45,16 @@ def leaf_values(n: int, sh_degree: int, seed: int, mu: float = 2.0, s: float = 1
     return sigma, sh
 
 
+def sg_lobes(K: int, seed: int, lam_range=(2.0, 12.0)) -> np.ndarray:
+    """K spherical-Gaussian lobes (K, 4) float32: unit axes drawn uniformly
+    on the sphere, bandwidths uniform in lam_range."""
+    rng = np.random.default_rng(seed)
+    p = rng.standard_normal((K, 3))
+    p /= np.linalg.norm(p, axis=1, keepdims=True)
+    lam = rng.uniform(lam_range[0], lam_range[1], (K, 1))
+    return np.concatenate([p, lam], 1).astype(np.float32)
+
+
 def perturb(sigma, sh, std: float, seed: int):
     """Adds N(0, std^2) noise to a copy of sigma and sh (float32)."""
     rng = np.random.default_rng(seed)

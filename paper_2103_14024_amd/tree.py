@@ -74,7 +74,8 @@ class Tree:
     the SH records (float32 or float16) as torch tensors, bound to a library
     handle.  The handle borrows the tensors; this object keeps them alive."""
 
-    def __init__(self, depth, sh_degree, child, sigma, sh, center=(0.0, 0.0, 0.0), half=1.0, perm=None):
+    def __init__(self, depth, sh_degree, child, sigma, sh, center=(0.0, 0.0, 0.0), half=1.0, perm=None,
+                 lobes=None):
         import torch
 
         self.depth, self.sh_degree = int(depth), int(sh_degree)
@@ -99,11 +100,20 @@ class Tree:
         self.stride = int(sh.shape[1])
         self.child, self.sigma, self.sh = child, sigma, sh
         self.perm = perm
+        self.lobes = lobes
         self.desc = make_desc(depth, sh_degree, center, half, self.dtype, self.stride)
         h = ctypes.c_void_p()
-        L.call("po_tree_bind", ctypes.byref(self.desc), int(child.shape[0]), child.data_ptr(), self.n_leaves,
-               sigma.data_ptr() if self.n_leaves else None, sh.data_ptr() if self.n_leaves else None,
-               ctypes.byref(h))
+        leaf_ptrs = (sigma.data_ptr() if self.n_leaves else None, sh.data_ptr() if self.n_leaves else None)
+        if lobes is None:
+            L.call("po_tree_bind", ctypes.byref(self.desc), int(child.shape[0]), child.data_ptr(), self.n_leaves,
+                   *leaf_ptrs, ctypes.byref(h))
+        else:
+            # spherical-Gaussian colour basis: (K, 4) float32 device lobes (axis, bandwidth)
+            if not (lobes.is_cuda and lobes.dtype == torch.float32 and tuple(lobes.shape) == (self.K, 4)
+                    and lobes.is_contiguous()):
+                raise ValueError(f"lobes must be a contiguous float32 ({self.K}, 4) device tensor")
+            L.call("po_tree_bind_sg", ctypes.byref(self.desc), int(child.shape[0]), child.data_ptr(),
+                   self.n_leaves, *leaf_ptrs, lobes.data_ptr(), ctypes.byref(h))
         self._h = h
 
     @property
@@ -125,10 +135,11 @@ class Tree:
 
     @classmethod
     def from_cells(cls, depth, sh_degree, cells, sigma, sh, center=(0.0, 0.0, 0.0), half=1.0, dtype="f32",
-                   device="cuda", stride=None):
+                   device="cuda", stride=None, lobes=None):
         """Builds the tree on the host from leaf cells (level, i, j, k) with
         values in the caller's order, reorders the values into leaf order and
-        uploads everything to `device`."""
+        uploads everything to `device`.  lobes: None (SH colour basis) or
+        (K, 4) spherical-Gaussian lobes (axis, bandwidth)."""
         import torch
 
         code = _dtype_code(dtype)
@@ -149,12 +160,16 @@ class Tree:
         t_child = torch.from_numpy(child).to(dev)
         t_sig = torch.from_numpy(np.ascontiguousarray(sig)).to(dev)
         t_sh = torch.from_numpy(rec).to(dev)
-        return cls(depth, sh_degree, t_child, t_sig, t_sh, center, half, perm=perm)
+        t_lobes = None
+        if lobes is not None:
+            t_lobes = torch.from_numpy(np.ascontiguousarray(np.asarray(lobes, np.float32).reshape(K, 4))).to(dev)
+        return cls(depth, sh_degree, t_child, t_sig, t_sh, center, half, perm=perm, lobes=t_lobes)
 
     @classmethod
     def from_scene(cls, scene: dict, dtype="f32", device="cuda", stride=None):
         return cls.from_cells(scene["depth"], scene["sh_degree"], scene["cells"], scene["sigma"], scene["sh"],
-                              scene["center"], scene["half"], dtype=dtype, device=device, stride=stride)
+                              scene["center"], scene["half"], dtype=dtype, device=device, stride=stride,
+                              lobes=scene.get("lobes"))
 
     def leaf_values(self):
         """(sigma (n,), sh (n, 3, K)) as float32 NumPy arrays in the caller's cell order."""

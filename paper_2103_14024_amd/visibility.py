@@ -62,6 +62,7 @@ def prune(tree: Tree, weight, tau: float):
     sig = tree.sigma.float().cpu().numpy()[kept]
     sh = tree.sh[:, :3 * tree.K].float().cpu().numpy()[kept]
     dtype = "f16" if tree.dtype == L.PO_F16 else "f32"
+    lobes = tree.lobes.cpu().numpy() if tree.lobes is not None else None
     new = Tree.from_cells(tree.depth, tree.sh_degree, cells[kept], sig, sh, tree.center, tree.half, dtype=dtype,
-                          device=tree.sigma.device, stride=tree.stride)
+                          device=tree.sigma.device, stride=tree.stride, lobes=lobes)
     return new, kept
