@@ -463,7 +463,8 @@ po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_rend
     j.tile_begin = 0;
     j.block_begin = 0;
     j.tiles_x = (cam->width + PO_TILE - 1) / PO_TILE;
-    hipError_t e = po_launch_camera_jobs(t, 1, &j, 4 * tiles_of(cam), po_view_opts(j.op, j.aux), (hipStream_t)stream);
+    hipError_t e = po_launch_camera_jobs(t, 1, &j, 4 * tiles_of(cam), po_fwd_variant(j.op, j.aux, t->kt),
+                                         (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "render_camera launch");
     return ok();
 }
@@ -542,8 +543,8 @@ po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream) {
     // group jobs by kernel variant, one launch per group, in order of first appearance
     auto variant = [&](int q) {
         const po_job& J = jobs[q];
-        const bool view = po_view_opts(kopts(J.tree, &J.opts), (J.opts.flags & PO_OUT_AUX) ? J.d_aux : nullptr);
-        return 2 * po_plan_id(J.tree) + (view ? 1 : 0);
+        const float* aux = (J.opts.flags & PO_OUT_AUX) ? J.d_aux : nullptr;
+        return 3 * po_plan_id(J.tree) + po_fwd_variant(kopts(J.tree, &J.opts), aux, J.tree->kt);
     };
     bool done[PO_BATCH_MAX_JOBS] = {false};
     for (int i = 0; i < n_jobs; ++i) {
@@ -570,7 +571,7 @@ po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream) {
             blocks += 4 * nt;
         }
         if (nj == 0) continue;
-        hipError_t e = po_launch_camera_jobs(jobs[i].tree, nj, kj, blocks, (plan & 1) != 0, (hipStream_t)stream);
+        hipError_t e = po_launch_camera_jobs(jobs[i].tree, nj, kj, blocks, plan % 3, (hipStream_t)stream);
         if (e != hipSuccess) return device_fail(e, "render_batch launch");
     }
     return ok();

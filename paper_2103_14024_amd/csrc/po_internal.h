@@ -39,6 +39,14 @@ inline bool po_view_opts(const KOpts& k, const float* aux) {
            k.clip[3] != 0.0f;
 }
 
+// Compiled variants of the forward render: plain with the SH basis, plain
+// with spherical Gaussians, and the viewer kernel (either basis, chosen per
+// tree at run time).  The plain kernels carry no code for the other basis.
+enum { PO_FWD_SH = 0, PO_FWD_SG = 1, PO_FWD_VIEW = 2 };
+inline int po_fwd_variant(const KOpts& k, const float* aux, const KTree& t) {
+    return po_view_opts(k, aux) ? PO_FWD_VIEW : (t.lobes ? PO_FWD_SG : PO_FWD_SH);
+}
+
 struct KCam {
     float c2w[12];
     int32_t W, H;
@@ -77,9 +85,9 @@ hipError_t po_launch_backward(const po_tree* t, int64_t n, const float* o, const
                               const KOpts& op, const float* rgb_fwd, const float* grad_rgb,
                               float* grad_sigma, float* grad_sh, hipStream_t s);
 // Renders camera jobs that all share dtype, K and vec_bytes (at most
-// PO_BATCH_MAX_JOBS) and the same po_view_opts; n_blocks counts workgroups,
-// four per 16x16 tile.
-hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, bool view,
+// PO_BATCH_MAX_JOBS) and the same po_fwd_variant; n_blocks counts
+// workgroups, four per 16x16 tile.
+hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, int variant,
                                  hipStream_t s);
 hipError_t po_launch_camera_rays(const KCam& cam, float* o, float* d, hipStream_t s);
 // Visibility filter: mode 0 alpha, 1 contribution; weight[n_leaves] raised in place, alpha[H*W] or nullptr.

@@ -486,9 +486,9 @@ struct FwdSampler {
 };
 
 // Renders one ray: colour (background included), final T, samples, steps
-// and, with VIEW, the expected termination distance, SH subsets and the
-// slicing plane.
-template <typename T, int K, int VEC, int NL, bool VIEW>
+// and, in the viewer variant, the expected termination distance, SH subsets
+// and the slicing plane.  V is a PO_FWD_* variant.
+template <typename T, int K, int VEC, int NL, int V>
 __device__ __forceinline__ void render_one(const KTree& tr, const KOpts& op, const double (&o)[3],
                                            const double (&d)[3], int* __restrict__ stk, float (&C)[3], float& Tr,
                                            int& ns, int& steps, float& dep) {
@@ -497,6 +497,7 @@ __device__ __forceinline__ void render_one(const KTree& tr, const KOpts& op, con
     ns = 0;
     steps = 0;
     dep = 0.0f;
+    constexpr bool VIEW = V == PO_FWD_VIEW;
     Ray r;
     double s_lo = 0.0, s_hi = 1e300;
     if constexpr (VIEW) clip_range(op, o, d, s_lo, s_hi);
@@ -508,7 +509,12 @@ __device__ __forceinline__ void render_one(const KTree& tr, const KOpts& op, con
         smp.sh_end = tr.sh_bytes;
         smp.rec_bytes = (uint32_t)tr.stride * (uint32_t)sizeof(T);
         smp.stopT = op.stop_T;
-        colour_basis<K>(tr, r.dn[0], r.dn[1], r.dn[2], smp.Y);
+        if constexpr (V == PO_FWD_SH)
+            sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], smp.Y);
+        else if constexpr (V == PO_FWD_SG)
+            sg_basis<K>(tr.lobes, r.dn[0], r.dn[1], r.dn[2], smp.Y);
+        else
+            colour_basis<K>(tr, r.dn[0], r.dn[1], r.dn[2], smp.Y);
         if constexpr (VIEW) {
 #pragma unroll
             for (int k = 0; k < K; ++k)
@@ -537,7 +543,7 @@ __device__ __forceinline__ int64_t xcd_swizzle(int64_t b, int64_t n_logical) {
     return l < n_logical ? l : -1;
 }
 
-template <typename T, int K, int VEC, int NL, bool VIEW>
+template <typename T, int K, int VEC, int NL, int V>
 __global__ __launch_bounds__(kBlock) void k_render_rays(KTree tr, int64_t n, int64_t n_blocks,
                                                         const float* __restrict__ o,
                                                         const float* __restrict__ d, KOpts op,
@@ -551,11 +557,11 @@ __global__ __launch_bounds__(kBlock) void k_render_rays(KTree tr, int64_t n, int
     float C[3], Tr, dep;
     int ns, steps;
     extern __shared__ int po_stack[];
-    render_one<T, K, VEC, NL, VIEW>(tr, op, ro, rd, po_stack + threadIdx.x, C, Tr, ns, steps, dep);
+    render_one<T, K, VEC, NL, V>(tr, op, ro, rd, po_stack + threadIdx.x, C, Tr, ns, steps, dep);
     rgb[3 * i + 0] = C[0];
     rgb[3 * i + 1] = C[1];
     rgb[3 * i + 2] = C[2];
-    if constexpr (VIEW) {
+    if constexpr (V == PO_FWD_VIEW) {
         if (aux) {
             aux[4 * i + 0] = Tr;
             aux[4 * i + 1] = (float)ns;
@@ -603,7 +609,7 @@ static_assert(sizeof(KBatch<PO_BATCH_MAX_JOBS>) <= 4096, "batched kernel argumen
 
 // Camera jobs: a 16x16 tile is rendered by four single-wave workgroups, one
 // per 8x8 quadrant; lane l takes the pixel (l & 7, l >> 3) of its quadrant.
-template <typename T, int K, int VEC, int NL, int MAXJ, bool VIEW>
+template <typename T, int K, int VEC, int NL, int MAXJ, int V>
 __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
     const int64_t b = xcd_swizzle(blockIdx.x, B.n_blocks);
     if (b < 0) return;
@@ -625,12 +631,12 @@ __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
     float C[3], Tr, dep;
     int ns, steps;
     extern __shared__ int po_stack[];
-    render_one<T, K, VEC, NL, VIEW>(J.tr, J.op, ro, rd, po_stack + threadIdx.x, C, Tr, ns, steps, dep);
+    render_one<T, K, VEC, NL, V>(J.tr, J.op, ro, rd, po_stack + threadIdx.x, C, Tr, ns, steps, dep);
     const size_t p = (size_t)py * J.cam.W + px;
     J.rgb[3 * p + 0] = C[0];
     J.rgb[3 * p + 1] = C[1];
     J.rgb[3 * p + 2] = C[2];
-    if constexpr (VIEW) {
+    if constexpr (V == PO_FWD_VIEW) {
         if (J.aux) {
             J.aux[4 * p + 0] = Tr;
             J.aux[4 * p + 1] = (float)ns;
@@ -644,11 +650,16 @@ __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
 // first pass; this second pass keeps the prefix P_i of w_k c_k, so that
 // dC/dsigma_i = delta_i (c_i T_{i+1} - (C - P_i)) (zero where the raw density
 // is <= 0) and dC/dk = w_i c_i (1 - c_i) Y, contracted with dL/dC and added
-// to the leaf gradients with float atomics.
+// to the leaf gradients with float atomics.  The density gradient is added
+// by its own lane; the 3K coefficient gradients of the wave's samples are
+// staged in LDS and added cooperatively (flush), so that one atomic
+// instruction covers one or two records instead of 64 scattered ones.
 template <int K, int VEC, int NL>
 struct BwdSampler {
     static constexpr int NW = Words<float, NL>::N;
     static constexpr bool kClip = false;
+    static constexpr int NE = 3 * K;
+    static constexpr int SW = (NE + 3) / 4 * 4;  // LDS slot: one sample's products
     __amdgpu_buffer_rsrc_t sig, shb;
     uint32_t sig_end, sh_end, rec_bytes;
     int stride;
@@ -657,7 +668,11 @@ struct BwdSampler {
     float g0, g1, g2, C0, C1, C2;
     float* gsig;
     float* gsh;
+    float* sprod;
+    int* sleaf;
     float Tl = 1.0f, P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
+    bool has = false;
+    float z0, z1, z2;
     // in flight
     int leaf;
     float raw, delta;
@@ -669,7 +684,6 @@ struct BwdSampler {
         load_words_buf<float, NL, VEC>(shb, l < 0 ? sh_end : (uint32_t)l * rec_bytes, w);
         delta = d;
     }
-    __device__ __forceinline__ void flush() {}
     __device__ __forceinline__ bool consume() {
         const float s = fmaxf(raw, 0.0f);
         if (!(s > 0.0f)) return false;  // no density: zero weight, and dC/dsigma is masked
@@ -686,18 +700,42 @@ struct BwdSampler {
         gs = fmaf(g1, c1 * Tn - (C1 - P1), gs);
         gs = fmaf(g2, c2 * Tn - (C2 - P2), gs);
         atomicAdd(gsig + leaf, gs * delta);
-        float* gk = gsh + (size_t)leaf * stride;
-        const float z0 = g0 * wgt * c0 * (1.0f - c0);
-        const float z1 = g1 * wgt * c1 * (1.0f - c1);
-        const float z2 = g2 * wgt * c2 * (1.0f - c2);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            atomicAdd(gk + k, z0 * Y[k]);
-            atomicAdd(gk + K + k, z1 * Y[k]);
-            atomicAdd(gk + 2 * K + k, z2 * Y[k]);
-        }
+        z0 = g0 * wgt * c0 * (1.0f - c0);
+        z1 = g1 * wgt * c1 * (1.0f - c1);
+        z2 = g2 * wgt * c2 * (1.0f - c2);
+        has = true;
         Tl = Tn;
         return Tl < stopT;
+    }
+    // Runs with every lane still walking: the lanes that composited a sample
+    // write its 3K coefficient gradients to consecutive LDS slots, then all
+    // active lanes add them to the leaves, consecutive lanes taking
+    // consecutive coefficients of a record.
+    __device__ __forceinline__ void flush() {
+        const uint64_t m = __ballot(has);
+        if (m == 0) return;
+        if (has) {
+            const int slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            float* dst = sprod + slot * SW;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                dst[k] = z0 * Y[k];
+                dst[K + k] = z1 * Y[k];
+                dst[2 * K + k] = z2 * Y[k];
+            }
+            sleaf[slot] = leaf;
+            has = false;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t act = __ballot(1);
+        const int na = __popcll(act);
+        const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+        const int total = __popcll(m) * SW;
+        for (int it = r; it < total; it += na) {
+            const int j = it / SW, e = it - j * SW;
+            if (e < NE) atomicAdd(gsh + (size_t)sleaf[j] * stride + e, sprod[it]);
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 };
 
@@ -734,6 +772,10 @@ __global__ __launch_bounds__(kBlock) void k_backward(KTree tr, int64_t n, int64_
     smp.stopT = op.stop_T;
     smp.gsig = gsig;
     smp.gsh = gsh;
+    __shared__ float s_prod[kBlock * BwdSampler<K, VEC, NL>::SW];
+    __shared__ int s_leaf[kBlock];
+    smp.sprod = s_prod;
+    smp.sleaf = s_leaf;
     colour_basis<K>(tr, r.dn[0], r.dn[1], r.dn[2], smp.Y);
     extern __shared__ int po_stack[];
     march(tr, r, op.max_steps, po_stack + threadIdx.x, smp);
@@ -865,26 +907,29 @@ hipError_t rays_t(const po_tree* t, int64_t n, const float* o, const float* d, c
     dim3 grid((unsigned)grid_for(nb)), block(kBlock);
     const size_t lds = stack_bytes(t->kt.depth);
     const bool fast = use_fast<T, K>(t);
-    if (po_view_opts(op, aux)) {
-        if (fast)
-            hipLaunchKernelGGL((k_render_rays<T, K, P::FAST_VEC, P::FAST_NL, true>), grid, block, lds, s, t->kt, n,
-                               nb, o, d, op, rgb, aux);
-        else
-            hipLaunchKernelGGL((k_render_rays<T, K, 4, P::GEN_NL, true>), grid, block, lds, s, t->kt, n, nb, o, d,
-                               op, rgb, aux);
-    } else {
-        if (fast)
-            hipLaunchKernelGGL((k_render_rays<T, K, P::FAST_VEC, P::FAST_NL, false>), grid, block, lds, s, t->kt, n,
-                               nb, o, d, op, rgb, nullptr);
-        else
-            hipLaunchKernelGGL((k_render_rays<T, K, 4, P::GEN_NL, false>), grid, block, lds, s, t->kt, n, nb, o, d,
-                               op, rgb, nullptr);
-    }
+    const int v = po_fwd_variant(op, aux, t->kt);
+    if (v != PO_FWD_VIEW) aux = nullptr;
+#define PO_RAYS(V_)                                                                                              \
+    do {                                                                                                        \
+        if (fast)                                                                                               \
+            hipLaunchKernelGGL((k_render_rays<T, K, P::FAST_VEC, P::FAST_NL, V_>), grid, block, lds, s, t->kt, n, \
+                               nb, o, d, op, rgb, aux);                                                         \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_render_rays<T, K, 4, P::GEN_NL, V_>), grid, block, lds, s, t->kt, n, nb, o, d, \
+                               op, rgb, aux);                                                                   \
+    } while (0)
+    if (v == PO_FWD_VIEW)
+        PO_RAYS(PO_FWD_VIEW);
+    else if (v == PO_FWD_SG)
+        PO_RAYS(PO_FWD_SG);
+    else
+        PO_RAYS(PO_FWD_SH);
+#undef PO_RAYS
     return hipGetLastError();
 }
 
 template <typename T, int K, int MAXJ>
-hipError_t camera_t(const po_tree* t, int n_jobs, KJob* jobs, int n_blocks, bool view, hipStream_t s) {
+hipError_t camera_t(const po_tree* t, int n_jobs, KJob* jobs, int n_blocks, int variant, hipStream_t s) {
     using P = Plan<T, K>;
     KBatch<MAXJ> B;
     for (int j = 0; j < n_jobs; ++j) B.job[j] = jobs[j];
@@ -896,17 +941,20 @@ hipError_t camera_t(const po_tree* t, int n_jobs, KJob* jobs, int n_blocks, bool
     dim3 grid((unsigned)grid_for(n_blocks)), block(kBlock);
     const size_t lds = stack_bytes(depth);
     const bool fast = use_fast<T, K>(t);
-    if (view) {
-        if (fast)
-            hipLaunchKernelGGL((k_render_camera<T, K, P::FAST_VEC, P::FAST_NL, MAXJ, true>), grid, block, lds, s, B);
-        else
-            hipLaunchKernelGGL((k_render_camera<T, K, 4, P::GEN_NL, MAXJ, true>), grid, block, lds, s, B);
-    } else {
-        if (fast)
-            hipLaunchKernelGGL((k_render_camera<T, K, P::FAST_VEC, P::FAST_NL, MAXJ, false>), grid, block, lds, s, B);
-        else
-            hipLaunchKernelGGL((k_render_camera<T, K, 4, P::GEN_NL, MAXJ, false>), grid, block, lds, s, B);
-    }
+#define PO_CAM(V_)                                                                                               \
+    do {                                                                                                        \
+        if (fast)                                                                                               \
+            hipLaunchKernelGGL((k_render_camera<T, K, P::FAST_VEC, P::FAST_NL, MAXJ, V_>), grid, block, lds, s, B); \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_render_camera<T, K, 4, P::GEN_NL, MAXJ, V_>), grid, block, lds, s, B);        \
+    } while (0)
+    if (variant == PO_FWD_VIEW)
+        PO_CAM(PO_FWD_VIEW);
+    else if (variant == PO_FWD_SG)
+        PO_CAM(PO_FWD_SG);
+    else
+        PO_CAM(PO_FWD_SH);
+#undef PO_CAM
     return hipGetLastError();
 }
 
@@ -946,19 +994,19 @@ hipError_t po_launch_rays(const po_tree* t, int64_t n, const float* o, const flo
     }
 }
 
-hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, bool view,
+hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, int variant,
                                  hipStream_t s) {
     if (n_jobs == 1) {
         if (first->desc.dtype == PO_F32) {
-            PO_DISPATCH_K(first->K, (camera_t<float, KK, 1>(first, n_jobs, jobs, n_blocks, view, s)));
+            PO_DISPATCH_K(first->K, (camera_t<float, KK, 1>(first, n_jobs, jobs, n_blocks, variant, s)));
         } else {
-            PO_DISPATCH_K(first->K, (camera_t<__half, KK, 1>(first, n_jobs, jobs, n_blocks, view, s)));
+            PO_DISPATCH_K(first->K, (camera_t<__half, KK, 1>(first, n_jobs, jobs, n_blocks, variant, s)));
         }
     }
     if (first->desc.dtype == PO_F32) {
-        PO_DISPATCH_K(first->K, (camera_t<float, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, view, s)));
+        PO_DISPATCH_K(first->K, (camera_t<float, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, variant, s)));
     } else {
-        PO_DISPATCH_K(first->K, (camera_t<__half, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, view, s)));
+        PO_DISPATCH_K(first->K, (camera_t<__half, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, variant, s)));
     }
 }
 
