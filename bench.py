@@ -212,6 +212,100 @@ def serve_leg(po, scenes, rates=(50, 100, 200, 350, 500), n_requests=300, budget
             "by_rate": per_rate}
 
 
+def _time_frames(po, tree, cams, n, **kw):
+    """ms per frame of render_camera over n frames (HIP events, after 3 warm-up frames)."""
+    import torch
+
+    img = torch.empty((cams[0].height, cams[0].width, 3), dtype=torch.float32, device="cuda")
+    aux = None
+    if kw.get("aux"):
+        aux = torch.empty((cams[0].height, cams[0].width, po.AUX_WIDTH), dtype=torch.float32, device="cuda")
+    for i in range(3):
+        po.render_camera(tree, cams[i % len(cams)], stop_T=STOP_T, out=img, aux_out=aux, **kw)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(n):
+        po.render_camera(tree, cams[i % len(cams)], stop_T=STOP_T, out=img, aux_out=aux, **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def basis_leg(po, scenes, scene, cams, frames=50):
+    """Colour-basis sweep (App. A basis ablation): the depth-9 geometry with
+    SH-9, SH-16, SH-25 and SG-25 leaves (fresh N(0, 0.5^2) coefficients,
+    lognormal densities as the main workload; SG lobes seeded), float32 and
+    float16 leaves, 800x800 frames of the main poses."""
+    res = {}
+    for name, deg, sg in (("SH-9", 2, False), ("SH-16", 3, False), ("SH-25", 4, False), ("SG-25", 4, True)):
+        sig, sh = scenes.leaf_values(len(scene["cells"]), deg, 1)
+        sd = dict(scene, sh_degree=deg, sigma=sig, sh=sh)
+        if sg:
+            sd["lobes"] = scenes.sg_lobes((deg + 1) ** 2, 17)
+        row = {}
+        for dt in ("f32", "f16"):
+            tree = po.Tree.from_scene(sd, dtype=dt)
+            ms = _time_frames(po, tree, cams, frames)
+            row[dt] = {"fps": round(1e3 / ms, 1), "leaf_bytes": (4 if dt == "f32" else 2) * (1 + 3 * tree.K),
+                       "tree_mb": round(tree.nbytes() / 1e6, 1)}
+            del tree
+        res[name] = row
+        log(f"basis {name}: {row}")
+    return {"workload": "depth-9 blob band geometry, 800x800, %d frames per variant" % frames, "by_basis": res,
+            "paper_context": {"fps": {"SH-9": 262, "SH-16": 168, "SH-25": 128, "SG-25": 151},
+                              "hardware": "Tesla V100", "workload": "NeRF-synthetic real scenes"}}
+
+
+def view_leg(po, tree, cams, frames=50):
+    """Viewer outputs (Sec. 5.5) on the main workload: cost of the depth and
+    alpha maps (aux output), of an SH subset and of a slicing plane relative
+    to the plain render."""
+    base = _time_frames(po, tree, cams, frames)
+    depth = _time_frames(po, tree, cams, frames, aux=True)
+    sub = _time_frames(po, tree, cams, frames, sh_off=0b1111111110000)
+    cut = _time_frames(po, tree, cams, frames, clip=(0.3, -0.5, 0.8, 0.05))
+    return {"fps_plain": round(1e3 / base, 1), "fps_depth_alpha": round(1e3 / depth, 1),
+            "fps_sh_subset": round(1e3 / sub, 1), "fps_slicing_plane": round(1e3 / cut, 1)}
+
+
+def filter_leg(po, tree, cams, tau=0.01):
+    """Visibility filter (Sec. 4.2 "Filtering") on the main tree: alpha renders
+    of the 800x800 poses raise each leaf's largest ray weight (atomic max);
+    then the leaves below tau are pruned and the tree rebuilt on the host.
+    Algorithmic bytes: per sample the density and the weight's read and
+    write (12 B float32)."""
+    import torch
+
+    w = torch.zeros(tree.n_leaves, dtype=torch.float32, device="cuda")
+    po.visibility.leaf_weights(tree, cams[:3], stop_T=STOP_T, weight=w)
+    w.zero_()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    po.visibility.leaf_weights(tree, cams, stop_T=STOP_T, weight=w)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / len(cams)
+    # samples per view from the render's aux pass (the filter walks the same segments)
+    aux = torch.empty((H, W, po.AUX_WIDTH), dtype=torch.float32, device="cuda")
+    n_samples = 0.0
+    for c in cams[:20]:
+        po.render_camera(tree, c, stop_T=STOP_T, aux=True, aux_out=aux)
+        n_samples += float(aux[..., po.AUX_SAMPLES].sum())
+    n_samples /= 20
+    t0 = time.perf_counter()
+    pruned, kept = po.visibility.prune(tree, w, tau)
+    t_prune = time.perf_counter() - t0
+    gbps = 12.0 * n_samples / (ms * 1e-3) / 1e9
+    return {"views": len(cams), "ms_per_view": round(ms, 4), "mrays_per_s": round(W * H / (ms * 1e3), 1),
+            "msamples_per_s": round(n_samples / (ms * 1e3), 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": round(gbps / HBM_PEAK_GBPS, 4), "alg_bytes_per_sample": 12},
+            "tau_w": tau, "leaves_kept": int(len(kept)), "leaves": int(tree.n_leaves),
+            "prune_rebuild_s": round(t_prune, 2)}
+
+
 def calib_copy(mib: int):
     """One plain device-to-device copy of `mib` MiB, for scaling the HBM
     traffic counters (it reads and writes exactly that many bytes)."""
@@ -237,6 +331,7 @@ def main():
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=300, help="requests per arrival rate")
+    ap.add_argument("--no-extra", action="store_true", help="skip the viewer, filter and basis-sweep legs")
     ap.add_argument("--profile", action="store_true",
                     help="time the float32 renders only (no sample-count pass, fp16 or CPU legs); no JSON line")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -290,11 +385,16 @@ def main():
         "lane_efficiency": round(r32["lane_efficiency"], 4),
         "roofline": {"bound": "hbm", "achieved": round(r32["alg_gbps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(r32["alg_gbps"] / HBM_PEAK_GBPS, 4), "traffic": traffic_gbps,
-                     "kernel": "k_render_camera<float,16,16,48,1>",
+                     "kernel": "k_render_camera<float,16,16,48,1,0>",
                      "alg_bytes_per_launch": int(r32["alg_bytes_per_launch"]),
                      "hbm_bytes_per_launch": None if tb is None else int(tb)},
         "paper_context": {"fps": 167.68, "hardware": "Tesla V100", "workload": "NeRF-synthetic real scenes"},
     }
+    if not args.no_extra:
+        out["view"] = view_leg(po, tree32, cams)
+        log(f"view: {out['view']}")
+        out["filter"] = filter_leg(po, tree32, cams[:100])
+        log(f"filter: {out['filter']}")
     del tree32
     torch.cuda.empty_cache()
     if not args.no_fp16:
@@ -308,6 +408,8 @@ def main():
                        "hbm_gbps": None if t16 is None else round(t16 / (r16["ms_per_step"] * 1e-3) / 1e9, 1),
                        "speedup_vs_fp32": round(r16["fps"] / r32["fps"], 3)}
         del tree16
+    if not args.no_extra:
+        out["basis"] = basis_leg(po, scenes, scene, cams)
     if not args.no_train:
         log("differentiation: direct octree optimisation")
         out["train"] = train_leg(po, scenes)
