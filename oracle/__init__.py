@@ -62,6 +62,10 @@ def _load():
     L.orc_render_rays_view.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp, _dp, _dp, ctypes.c_double,
                                        ctypes.c_uint32, _dp, _dp, _dp, _i64p, _dp]
     L.orc_leaf_weights.argtypes = [ctypes.c_void_p, ctypes.c_int64, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp]
+    L.orc_half_bits.restype = ctypes.c_uint16
+    L.orc_half_bits.argtypes = [ctypes.c_double]
+    L.orc_median_cut.restype = ctypes.c_int64
+    L.orc_median_cut.argtypes = [ctypes.c_int64, _dp, ctypes.c_int64, _i64p, ctypes.POINTER(ctypes.c_uint16)]
     L.orc_camera_rays.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, _dp, _dp]
     L.orc_render_camera.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -111,6 +115,50 @@ def sg_basis(lobes, dirs) -> np.ndarray:
     out = np.zeros((dirs.shape[0], lb.shape[0]), np.float64)
     for i in range(dirs.shape[0]):
         L.orc_sg_basis(lb.shape[0], _p(lb), _p(dirs[i]), _p(out[i]))
+    return out
+
+
+def half_bits(x: float) -> int:
+    """IEEE binary16 bits of x (round to nearest even)."""
+    return int(_load().orc_half_bits(float(x)))
+
+
+def median_cut(points, M: int):
+    """Median cut of points (n, 3) into at most M boxes: returns (idx (n,)
+    int64 box of each point, codebook (nb, 3) float16, nb)."""
+    L = _load()
+    pts = _d(points).reshape(-1, 3)
+    n = pts.shape[0]
+    idx = np.zeros(n, np.int64)
+    cb = np.zeros((max(M, 1), 3), np.uint16)
+    nb = L.orc_median_cut(n, _p(pts), int(M), _p(idx, _i64p), cb.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)))
+    if nb < 0:
+        raise MemoryError("oracle median cut")
+    return idx, cb[:nb].view(np.float16), int(nb)
+
+
+def codebook(sh, M: int):
+    """Codebook compression of leaf coefficients sh (n, 3, K): for each basis
+    function k the RGB triples (sh[:, :, k]) are median-cut into at most M
+    colours.  Returns (idx (n, K) int64, codebooks: list of K (nb_k, 3)
+    float16 arrays)."""
+    sh = np.asarray(sh)
+    n, _, K = sh.shape
+    idx = np.zeros((n, K), np.int64)
+    books = []
+    for k in range(K):
+        i_k, cb_k, _ = median_cut(sh[:, :, k], M)
+        idx[:, k] = i_k
+        books.append(cb_k)
+    return idx, books
+
+
+def codebook_decode(idx, books):
+    """Leaf coefficients (n, 3, K) float64 of a codebook tree."""
+    n, K = idx.shape
+    out = np.zeros((n, 3, K), np.float64)
+    for k in range(K):
+        out[:, :, k] = books[k].astype(np.float64)[idx[:, k]]
     return out
 
 

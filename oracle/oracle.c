@@ -33,7 +33,10 @@
  *     renders.
  *
  *   - the spherical-Gaussian colour basis of App. B.1 (learnable lobes,
- *     global to the tree) in place of the SH.
+ *     global to the tree) in place of the SH;
+ *   - the codebook compression of App. B.2: median-cut quantisation of each
+ *     basis function's RGB coefficients into at most 2^16 colours, stored as
+ *     float16, with a 16-bit index per leaf and basis function.
  *
  * Readings where the paper is silent (each is also listed in the design notes):
  *   - SH: P_l^m includes the Condon-Shortley phase; the argument of the basis
@@ -52,6 +55,15 @@
  *   - Slicing: only the part of each ray inside the half-space n.x + w >= 0
  *     is rendered (clip = (n, w)); all-zero clip keeps everything.
  *   - SH subsets: bit k of sh_off drops basis function k from every channel.
+ *   - Median cut (App. B.2 names the algorithm only): start from one box
+ *     holding all points; repeatedly split the box whose largest side (max -
+ *     min of its points along an axis) is longest, ties to the lowest box
+ *     number, along that side (ties to the lowest axis); the lower half is
+ *     the floor(m/2) points that come first in the order (coordinate, point
+ *     index) and keeps the box number, the upper half gets the next number;
+ *     boxes of one point or zero extent are not split; stop at M boxes.  A
+ *     box's colour is the mean of its points, summed in double precision in
+ *     ascending point order and rounded to float16 (round to nearest even).
  *   - SG basis: G_j(d) = exp(lambda_j (d . p_j / |p_j| - 1)) with the lobe
  *     axis a 3-vector (the paper's "p in R^2" parametrises the sphere), one
  *     set of lobes per tree, the colour the sigmoid of sum_j k_j G_j(d).
@@ -643,6 +655,132 @@ void orc_leaf_weights(const orc_tree* t, int64_t n, const double* o, const doubl
         }
     }
     free(L.s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Codebook compression (App. B.2)                                           */
+/* ------------------------------------------------------------------------ */
+
+/* IEEE 754 binary16 bits of x, rounded to nearest with ties to even, from
+ * the format's definition: 1 sign bit, 5 exponent bits (bias 15), 10
+ * fraction bits; subnormals below 2^-14; overflow to infinity. */
+uint16_t orc_half_bits(double x) {
+    uint16_t sign = (uint16_t)(signbit(x) ? 0x8000u : 0u);
+    double a = fabs(x);
+    if (isnan(x)) return (uint16_t)(sign | 0x7e00u);
+    if (a >= 65520.0) return (uint16_t)(sign | 0x7c00u); /* rounds to infinity */
+    if (a < ldexp(1.0, -14)) {
+        /* subnormal: a multiple of 2^-24 */
+        double q = a * ldexp(1.0, 24);
+        double r = nearbyint(q); /* the default rounding mode: nearest, ties to even */
+        return (uint16_t)(sign | (uint16_t)r);
+    }
+    int e;
+    frexp(a, &e); /* a = f 2^e, f in [0.5, 1) */
+    int E = e - 1;                   /* a in [2^E, 2^(E+1)) */
+    double q = a * ldexp(1.0, 10 - E); /* in [1024, 2048) */
+    double r = nearbyint(q);
+    if (r >= 2048.0) { /* rounded up into the next binade */
+        r = 1024.0;
+        E += 1;
+    }
+    if (E > 15) return (uint16_t)(sign | 0x7c00u);
+    return (uint16_t)(sign | (uint16_t)((E + 15) << 10) | (uint16_t)((int)r - 1024));
+}
+
+typedef struct {
+    int64_t* pts;  /* member point indices */
+    int64_t n;
+    double extent; /* longest side */
+    int axis;      /* axis of the longest side */
+} orc_box;
+
+static const double* mc_points;
+static int mc_axis;
+
+static int mc_cmp(const void* pa, const void* pb) {
+    int64_t a = *(const int64_t*)pa, b = *(const int64_t*)pb;
+    double va = mc_points[3 * a + mc_axis], vb = mc_points[3 * b + mc_axis];
+    if (va < vb) return -1;
+    if (va > vb) return 1;
+    return (a > b) - (a < b);
+}
+
+static void mc_measure(const double* p, orc_box* b) {
+    b->extent = 0.0;
+    b->axis = 0;
+    if (b->n == 0) return;
+    for (int ax = 0; ax < 3; ++ax) {
+        double lo = p[3 * b->pts[0] + ax], hi = lo;
+        for (int64_t q = 1; q < b->n; ++q) {
+            double v = p[3 * b->pts[q] + ax];
+            if (v < lo) lo = v;
+            if (v > hi) hi = v;
+        }
+        if (hi - lo > b->extent) {
+            b->extent = hi - lo;
+            b->axis = ax;
+        }
+    }
+}
+
+/* Median cut of n points (n x 3, values exactly representable) into at most
+ * M boxes, by the rule stated at the top of this file.  Writes each point's
+ * box number to idx (n), the float16 bits of each box's mean colour to
+ * cb_bits (M x 3; boxes past the returned count are zero) and returns the
+ * number of boxes, or -1 on allocation failure.  Single-threaded, O(M) per
+ * split. */
+int64_t orc_median_cut(int64_t n, const double* points, int64_t M, int64_t* idx, uint16_t* cb_bits) {
+    for (int64_t i = 0; i < 3 * M; ++i) cb_bits[i] = 0;
+    if (n == 0 || M < 1) return 0;
+    orc_box* boxes = (orc_box*)calloc((size_t)M, sizeof(orc_box));
+    int64_t* all = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    if (!boxes || !all) {
+        free(boxes);
+        free(all);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; ++i) all[i] = i;
+    boxes[0].pts = all;
+    boxes[0].n = n;
+    mc_measure(points, &boxes[0]);
+    int64_t nb = 1;
+    mc_points = points;
+    while (nb < M) {
+        int64_t best = -1;
+        for (int64_t b = 0; b < nb; ++b) {
+            if (boxes[b].n < 2 || !(boxes[b].extent > 0.0)) continue;
+            if (best < 0 || boxes[b].extent > boxes[best].extent) best = b;
+        }
+        if (best < 0) break;
+        orc_box* B = &boxes[best];
+        mc_axis = B->axis;
+        qsort(B->pts, (size_t)B->n, sizeof(int64_t), mc_cmp);
+        int64_t lo_n = B->n / 2;
+        orc_box* U = &boxes[nb];
+        U->pts = B->pts + lo_n; /* the members stay in the shared array */
+        U->n = B->n - lo_n;
+        B->n = lo_n;
+        mc_measure(points, B);
+        mc_measure(points, U);
+        ++nb;
+    }
+    for (int64_t b = 0; b < nb; ++b)
+        for (int64_t q = 0; q < boxes[b].n; ++q) idx[boxes[b].pts[q]] = b;
+    double* sum = (double*)calloc((size_t)nb * 3, sizeof(double));
+    int64_t* cnt = (int64_t*)calloc((size_t)nb, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t b = idx[i];
+        for (int c = 0; c < 3; ++c) sum[3 * b + c] += points[3 * i + c];
+        cnt[b] += 1;
+    }
+    for (int64_t b = 0; b < nb; ++b)
+        for (int c = 0; c < 3; ++c) cb_bits[3 * b + c] = orc_half_bits(sum[3 * b + c] / (double)cnt[b]);
+    free(sum);
+    free(cnt);
+    free(all);
+    free(boxes);
+    return nb;
 }
 
 int orc_num_threads(void) {
