@@ -179,6 +179,21 @@ po_status po_tree_bind(const po_tree_desc* desc, int64_t n_nodes, const int32_t*
  * bound basis; sh_off then drops lobes.  Errors as for po_tree_bind. */
 po_status po_tree_bind_sg(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
                           const void* d_sigma, const void* d_sh, const float* d_lobes, po_tree** out);
+/* po_tree_bind_codebook: binds a tree whose leaf colours are compressed
+ * with per-basis-function codebooks (App. B.2; build them with
+ * po_codebook_build).  desc->dtype must be PO_F16: d_sigma holds the float16
+ * densities.  d_index [n_leaves][stride] uint16 replaces the SH records:
+ * entry k is the leaf's codebook position for basis function k (stride =
+ * desc->sh_stride, even and >= K; 0 means K rounded up to a multiple of 4).
+ * d_codebook [K][M][4] float16, 8-byte aligned: (r, g, b, unused) per entry.
+ * The colour of a leaf is that of an SH leaf with coefficient (c, k) =
+ * codebook[k][index[k]][c].  Camera, ray and batched renders and the
+ * visibility filter accept codebook trees (no aux outputs, sh_off or slicing
+ * plane); gradients do not.  An index >= M reads another basis function's
+ * entry, or zero past the end of the codebook.  Errors as for po_tree_bind. */
+po_status po_tree_bind_codebook(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
+                                const void* d_sigma, const uint16_t* d_index, const void* d_codebook, int32_t M,
+                                po_tree** out);
 po_status po_tree_destroy(po_tree* t);
 
 /* ------------------------------------------------------------------ render
@@ -260,6 +275,27 @@ typedef struct {
 po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream);
 /* Number of 16x16 tiles of a camera image. */
 po_status po_camera_tiles(const po_camera* cam, int32_t* n_tiles);
+
+/* -------------------------------------------------------------- compression
+ * po_codebook_build: host only.  The codebook compression of App. B.2:
+ * for each basis function k the RGB coefficient triples (coefficient (c, k)
+ * of h_coef[leaf][coef_stride], channel-major as in the SH records) of all
+ * leaves are quantised by median cut into at most M <= 65536 colours.  The
+ * cut is fixed exactly so that results are reproducible: repeatedly split the
+ * box whose longest side is longest (ties: lowest box number) along that side
+ * (ties: lowest axis), the lower half being the floor(m/2) points first in
+ * the order (coordinate, leaf index) and keeping the box number, the upper
+ * half taking the next number; boxes of one point or zero extent are not
+ * split.  A box's colour is the mean of its points, summed in double
+ * precision in leaf order and rounded to float16 (nearest, ties to even).
+ * Writes h_codebook[K][M][4] float16 bits (r, g, b, 0; unused entries 0),
+ * h_index[n_leaves][index_stride] uint16 (positions k >= K set to 0) and, if
+ * h_boxes is not NULL, the number of boxes used per basis function.  Uses up
+ * to 16 host threads; the result does not depend on their number.  Errors:
+ * PO_ERR_INVALID (bad sizes, NULL arrays, non-finite coefficients),
+ * PO_ERR_OOM. */
+po_status po_codebook_build(int64_t n_leaves, int32_t K, const float* h_coef, int64_t coef_stride, int32_t M,
+                            uint16_t* h_codebook, uint16_t* h_index, int64_t index_stride, int32_t* h_boxes);
 
 /* --------------------------------------------------------------- filtering
  * The visibility filter of the conversion from a dense density grid (Sec.

@@ -32,18 +32,18 @@ def build(verbose: bool = False) -> str:
     """Compiles every source under csrc/ into one shared library next to this file."""
     os.makedirs(os.path.join(PKG, "_build"), exist_ok=True)
     objs = []
-    for src in ("po_kernels.hip", "po_api.cpp"):
+    for src in ("po_kernels.hip", "po_api.cpp", "po_codebook.cpp"):
         obj = os.path.join(PKG, "_build", src + ".o")
         cmd = [hipcc(), *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [hipcc(), "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC, "-c",
+            cmd = [hipcc(), "-O2", "-std=c++17", "-fPIC", "-Wall", "-pthread", "-I", INCLUDE, "-I", CSRC, "-c",
                    os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -63,6 +63,8 @@ _SIGS = {
     "po_tree_validate": [ctypes.POINTER(po_tree_desc), _I64, _P, _I64, _P],
     "po_tree_bind": [ctypes.POINTER(po_tree_desc), _I64, _P, _I64, _P, _P, ctypes.POINTER(_P)],
     "po_tree_bind_sg": [ctypes.POINTER(po_tree_desc), _I64, _P, _I64, _P, _P, _P, ctypes.POINTER(_P)],
+    "po_tree_bind_codebook": [ctypes.POINTER(po_tree_desc), _I64, _P, _I64, _P, _P, _P, _I32, ctypes.POINTER(_P)],
+    "po_codebook_build": [_I64, _I32, _P, _I64, _I32, _P, _P, _I64, _P],
     "po_tree_destroy": [_P],
     "po_render_rays": [_P, _I64, _P, _P, ctypes.POINTER(po_render_opts), _P, _P, _P],
     "po_render_camera": [_P, ctypes.POINTER(po_camera), ctypes.POINTER(po_render_opts), _P, _P, _P],

@@ -41,9 +41,17 @@ po_status device_fail(hipError_t e, const char* what) {
 
 bool finite(float v) { return std::isfinite(v); }
 
+}  // namespace
+
+po_status po_report(po_status s, const char* msg) { return s == PO_OK ? ok() : fail(s, "%s", msg); }
+
+namespace {
+
 int elem_size(int32_t dtype) { return dtype == PO_F16 ? 2 : 4; }
 
-po_status check_desc(const po_tree_desc* d) {
+// codebook: the records are K uint16 indices per leaf (stride in uint16, 0 =
+// K rounded up to a multiple of 4) and the densities must be float16.
+po_status check_desc(const po_tree_desc* d, bool codebook = false) {
     if (!d) return fail(PO_ERR_INVALID, "tree description is NULL");
     if (d->depth < 1 || d->depth > PO_MAX_DEPTH)
         return fail(PO_ERR_INVALID, "depth %d outside [1, %d]", d->depth, PO_MAX_DEPTH);
@@ -55,6 +63,13 @@ po_status check_desc(const po_tree_desc* d) {
         if (!finite(d->center[k])) return fail(PO_ERR_INVALID, "center must be finite");
     if (d->dtype != PO_F32 && d->dtype != PO_F16) return fail(PO_ERR_INVALID, "unknown dtype %d", d->dtype);
     const int K = (d->sh_degree + 1) * (d->sh_degree + 1);
+    if (codebook) {
+        if (d->dtype != PO_F16) return fail(PO_ERR_INVALID, "codebook trees keep float16 densities (dtype PO_F16)");
+        const int stride = d->sh_stride ? d->sh_stride : (K + 3) / 4 * 4;
+        if (stride < K) return fail(PO_ERR_INVALID, "index stride %d < K = %d", stride, K);
+        if (stride % 2) return fail(PO_ERR_INVALID, "index stride %d must be even (whole 4-byte words)", stride);
+        return PO_OK;
+    }
     const int stride = d->sh_stride ? d->sh_stride : 3 * K;
     if (stride < 3 * K) return fail(PO_ERR_INVALID, "sh_stride %d < 3*K = %d", stride, 3 * K);
     if ((stride * elem_size(d->dtype)) % 4 != 0)
@@ -360,8 +375,10 @@ po_status po_tree_leaf_cells(const po_tree_desc* desc, int64_t n_nodes, const in
 }
 
 static po_status bind_impl(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
-                           const void* d_sigma, const void* d_sh, const float* d_lobes, po_tree** out) {
-    if (po_status s = check_desc(desc)) return s;
+                           const void* d_sigma, const void* d_sh, const float* d_lobes, const void* d_codebook,
+                           int32_t cb_entries, po_tree** out) {
+    const bool cb = d_codebook != nullptr;
+    if (po_status s = check_desc(desc, cb)) return s;
     if (!out) return fail(PO_ERR_INVALID, "out is NULL");
     if (n_nodes < 1 || n_nodes >= (1ll << 31) / 8) return fail(PO_ERR_INVALID, "n_nodes %lld out of range", (long long)n_nodes);
     if (n_leaves < 0 || n_leaves >= (1ll << 31) - 1) return fail(PO_ERR_INVALID, "n_leaves %lld out of range", (long long)n_leaves);
@@ -373,12 +390,15 @@ static po_status bind_impl(const po_tree_desc* desc, int64_t n_nodes, const int3
     {
         // the kernels address each array through a 32-bit buffer offset
         const int K = (desc->sh_degree + 1) * (desc->sh_degree + 1);
-        const int64_t stride = desc->sh_stride ? desc->sh_stride : 3 * K;
+        const int64_t stride = desc->sh_stride ? desc->sh_stride : (cb ? (K + 3) / 4 * 4 : 3 * K);
         const uint64_t lim = (1ull << 32) - 256;
         if ((uint64_t)n_nodes * 32u >= lim || (uint64_t)n_leaves * es >= lim ||
             (uint64_t)n_leaves * (uint64_t)stride * es >= lim)
             return fail(PO_ERR_UNSUPPORTED, "a tree array exceeds 4 GiB");
     }
+    if (cb && (cb_entries < 1 || cb_entries > 65536))
+        return fail(PO_ERR_INVALID, "codebook size %d outside [1, 65536]", cb_entries);
+    if (cb && ((uintptr_t)d_codebook) % 8) return fail(PO_ERR_INVALID, "codebook must be 8-byte aligned");
     po_tree* t = new (std::nothrow) po_tree();
     if (!t) return fail(PO_ERR_OOM, "tree handle allocation");
     t->desc = *desc;
@@ -388,7 +408,8 @@ static po_status bind_impl(const po_tree_desc* desc, int64_t n_nodes, const int3
     t->sigma = d_sigma;
     t->sh = d_sh;
     t->K = (desc->sh_degree + 1) * (desc->sh_degree + 1);
-    t->stride = desc->sh_stride ? desc->sh_stride : 3 * t->K;
+    t->codebook = cb;
+    t->stride = desc->sh_stride ? desc->sh_stride : (cb ? (t->K + 3) / 4 * 4 : 3 * t->K);
     const size_t rb = (size_t)t->stride * es;
     t->vec_bytes = 4;
     for (int v : {16, 8}) {
@@ -401,7 +422,11 @@ static po_status bind_impl(const po_tree_desc* desc, int64_t n_nodes, const int3
     k.child = d_child;
     k.sigma = d_sigma;
     k.sh = d_sh;
-    k.lobes = d_lobes;
+    if (cb)
+        k.codebook = d_codebook;
+    else
+        k.lobes = d_lobes;
+    k.cb_entries = cb ? cb_entries : 0;
     k.n_nodes = (int32_t)n_nodes;
     k.n_leaves = (int32_t)n_leaves;
     k.stride = t->stride;
@@ -416,14 +441,21 @@ static po_status bind_impl(const po_tree_desc* desc, int64_t n_nodes, const int3
 
 po_status po_tree_bind(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
                        const void* d_sigma, const void* d_sh, po_tree** out) {
-    return bind_impl(desc, n_nodes, d_child, n_leaves, d_sigma, d_sh, nullptr, out);
+    return bind_impl(desc, n_nodes, d_child, n_leaves, d_sigma, d_sh, nullptr, nullptr, 0, out);
+}
+
+po_status po_tree_bind_codebook(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
+                                const void* d_sigma, const uint16_t* d_index, const void* d_codebook, int32_t M,
+                                po_tree** out) {
+    if (!d_codebook) return fail(PO_ERR_INVALID, "codebook is NULL");
+    return bind_impl(desc, n_nodes, d_child, n_leaves, d_sigma, d_index, nullptr, d_codebook, M, out);
 }
 
 po_status po_tree_bind_sg(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
                           const void* d_sigma, const void* d_sh, const float* d_lobes, po_tree** out) {
     if (!d_lobes) return fail(PO_ERR_INVALID, "lobe array is NULL");
     if (((uintptr_t)d_lobes) % 16) return fail(PO_ERR_INVALID, "lobe array must be 16-byte aligned");
-    return bind_impl(desc, n_nodes, d_child, n_leaves, d_sigma, d_sh, d_lobes, out);
+    return bind_impl(desc, n_nodes, d_child, n_leaves, d_sigma, d_sh, d_lobes, nullptr, 0, out);
 }
 
 po_status po_tree_destroy(po_tree* t) {
@@ -441,6 +473,8 @@ po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, co
     if (!d_origins || !d_dirs || !d_rgb) return fail(PO_ERR_INVALID, "ray or output array is NULL");
     if ((opts->flags & PO_OUT_AUX) && !d_aux) return fail(PO_ERR_INVALID, "PO_OUT_AUX set but aux is NULL");
     float* aux = (opts->flags & PO_OUT_AUX) ? d_aux : nullptr;
+    if (t->codebook && po_view_opts(kopts(t, opts), aux))
+        return fail(PO_ERR_UNSUPPORTED, "codebook trees render without aux outputs, sh_off or a slicing plane");
     hipError_t e = po_launch_rays(t, n, d_origins, d_dirs, kopts(t, opts), d_rgb, aux, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "render_rays launch");
     return ok();
@@ -460,6 +494,8 @@ po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_rend
     j.op = kopts(t, opts);
     j.rgb = d_rgb;
     j.aux = (opts->flags & PO_OUT_AUX) ? d_aux : nullptr;
+    if (t->codebook && po_view_opts(j.op, j.aux))
+        return fail(PO_ERR_UNSUPPORTED, "codebook trees render without aux outputs, sh_off or a slicing plane");
     j.tile_begin = 0;
     j.block_begin = 0;
     j.tiles_x = (cam->width + PO_TILE - 1) / PO_TILE;
@@ -536,6 +572,8 @@ po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream) {
         if (po_status s = check_opts(&J.opts)) return fail(s, "job %d: %s", i, g_err.c_str());
         if (!J.d_rgb) return fail(PO_ERR_INVALID, "job %d: output image is NULL", i);
         if ((J.opts.flags & PO_OUT_AUX) && !J.d_aux) return fail(PO_ERR_INVALID, "job %d: PO_OUT_AUX set but aux is NULL", i);
+        if (J.tree->codebook && po_view_opts(kopts(J.tree, &J.opts), (J.opts.flags & PO_OUT_AUX) ? J.d_aux : nullptr))
+            return fail(PO_ERR_UNSUPPORTED, "job %d: codebook trees render without aux outputs, sh_off or a slicing plane", i);
         if (J.tile_begin < 0 || J.tile_end < J.tile_begin || J.tile_end > tiles_of(&J.cam))
             return fail(PO_ERR_INVALID, "job %d: tile range [%d, %d) outside [0, %d]", i, J.tile_begin, J.tile_end,
                         tiles_of(&J.cam));
@@ -544,7 +582,7 @@ po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream) {
     auto variant = [&](int q) {
         const po_job& J = jobs[q];
         const float* aux = (J.opts.flags & PO_OUT_AUX) ? J.d_aux : nullptr;
-        return 3 * po_plan_id(J.tree) + po_fwd_variant(kopts(J.tree, &J.opts), aux, J.tree->kt);
+        return 4 * po_plan_id(J.tree) + po_fwd_variant(kopts(J.tree, &J.opts), aux, J.tree->kt);
     };
     bool done[PO_BATCH_MAX_JOBS] = {false};
     for (int i = 0; i < n_jobs; ++i) {
@@ -571,7 +609,7 @@ po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream) {
             blocks += 4 * nt;
         }
         if (nj == 0) continue;
-        hipError_t e = po_launch_camera_jobs(jobs[i].tree, nj, kj, blocks, plan % 3, (hipStream_t)stream);
+        hipError_t e = po_launch_camera_jobs(jobs[i].tree, nj, kj, blocks, plan % 4, (hipStream_t)stream);
         if (e != hipSuccess) return device_fail(e, "render_batch launch");
     }
     return ok();

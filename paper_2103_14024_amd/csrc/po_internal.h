@@ -12,11 +12,15 @@ struct KTree {
     const int32_t* child;   // [n_nodes][8]
     const void* sigma;      // [n_leaves] float or half
     const void* sh;         // [n_leaves][stride] float or half
-    const float* lobes;     // nullptr: SH colour basis; else [K][4] spherical-Gaussian lobes
+    union {                 // a tree has SG lobes or a codebook, never both
+        const float* lobes;     // cb_entries == 0: nullptr (SH basis) or [K][4] spherical-Gaussian lobes
+        const void* codebook;   // cb_entries > 0: [K][cb_entries][4] float16 colours; sh holds uint16 indices
+    };
     int32_t n_nodes;
     int32_t n_leaves;
     int32_t stride;         // elements per SH record
     int32_t depth;          // D
+    int32_t cb_entries;     // codebook entries per basis function (0: no codebook)
     uint32_t sigma_bytes;   // n_leaves * element size (< 2^32)
     uint32_t sh_bytes;      // n_leaves * stride * element size (< 2^32 - 256)
     double lo[3];           // box minimum corner, world units
@@ -42,8 +46,10 @@ inline bool po_view_opts(const KOpts& k, const float* aux) {
 // Compiled variants of the forward render: plain with the SH basis, plain
 // with spherical Gaussians, and the viewer kernel (either basis, chosen per
 // tree at run time).  The plain kernels carry no code for the other basis.
-enum { PO_FWD_SH = 0, PO_FWD_SG = 1, PO_FWD_VIEW = 2 };
+// Codebook trees render with PO_FWD_CB and take no viewer options.
+enum { PO_FWD_SH = 0, PO_FWD_SG = 1, PO_FWD_VIEW = 2, PO_FWD_CB = 3 };
 inline int po_fwd_variant(const KOpts& k, const float* aux, const KTree& t) {
+    if (t.cb_entries > 0) return PO_FWD_CB;
     return po_view_opts(k, aux) ? PO_FWD_VIEW : (t.lobes ? PO_FWD_SG : PO_FWD_SH);
 }
 
@@ -75,8 +81,12 @@ struct po_tree {
     int32_t K;              // coefficients per channel
     int32_t stride;         // elements per SH record
     int32_t vec_bytes;      // widest aligned load of a record: 16, 8 or 4
+    bool codebook;          // records are codebook indices (float16 densities)
     KTree kt;
 };
+
+// Sets the thread's po_last_error message (cleared for PO_OK) and returns s.
+po_status po_report(po_status s, const char* msg);
 
 // Launchers (po_kernels.hip).  Arguments are validated by the caller.
 hipError_t po_launch_rays(const po_tree* t, int64_t n, const float* o, const float* d,

@@ -23,6 +23,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "po_internal.h"
 
 __device__ unsigned long long g_po_errors = 0;
@@ -485,6 +487,61 @@ struct FwdSampler {
     }
 };
 
+// Codebook leaves (App. B.2): the record holds one 16-bit codebook position
+// per basis function; consume() gathers the K float16 colours (8 bytes each,
+// from the per-basis codebooks) and shades as an SH leaf.  The gathers are in
+// flight together with the next cell's entry prefetch, which the walk waits
+// for next anyway.
+template <int K, int VEC, int NL>
+struct CbSampler {
+    static constexpr int NW = Words<__half, NL>::N;
+    static constexpr bool kClip = false;
+    __amdgpu_buffer_rsrc_t sig, shb, cb;
+    uint32_t sig_end, sh_end, rec_bytes, cb_basis_bytes;
+    float stopT;
+    float Y[K];
+    float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, Tl = 1.0f;
+    float dep = 0.0f;
+    int ns = 0;
+    // in flight
+    float raw, delta;
+    uint32_t w[NW];
+
+    __device__ __forceinline__ void issue(int leaf, float d, float) {
+        raw = sigma_buf(sig, leaf < 0 ? sig_end : (uint32_t)leaf * 2u, (__half*)nullptr);
+        load_words_buf<__half, NL, VEC>(shb, leaf < 0 ? sh_end : (uint32_t)leaf * rec_bytes, w);
+        delta = d;
+    }
+    __device__ __forceinline__ void flush() {}
+    __device__ __forceinline__ bool consume() {
+        ++ns;
+        const float s = fmaxf(raw, 0.0f);
+        if (!(s > 0.0f)) return false;
+        uint32_t e0[K], e1[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t pos = (w[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+            const auto q = __builtin_amdgcn_raw_buffer_load_b64(cb, (uint32_t)k * cb_basis_bytes + pos * 8u, 0, 0);
+            e0[k] = q[0];
+            e1[k] = q[1];
+        }
+        float z0 = 0.0f, z1 = 0.0f, z2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            z0 = fmaf(__half2float(__ushort_as_half((unsigned short)(e0[k] & 0xffffu))), Y[k], z0);
+            z1 = fmaf(__half2float(__ushort_as_half((unsigned short)(e0[k] >> 16))), Y[k], z1);
+            z2 = fmaf(__half2float(__ushort_as_half((unsigned short)(e1[k] & 0xffffu))), Y[k], z2);
+        }
+        const float ex = __expf(-(s * delta));
+        const float wgt = Tl * (1.0f - ex);
+        c0 = fmaf(wgt, sigmoid(z0), c0);
+        c1 = fmaf(wgt, sigmoid(z1), c1);
+        c2 = fmaf(wgt, sigmoid(z2), c2);
+        Tl = Tl * ex;
+        return Tl < stopT;
+    }
+};
+
 // Renders one ray: colour (background included), final T, samples, steps
 // and, in the viewer variant, the expected termination distance, SH subsets
 // and the slicing plane.  V is a PO_FWD_* variant.
@@ -502,14 +559,19 @@ __device__ __forceinline__ void render_one(const KTree& tr, const KOpts& op, con
     double s_lo = 0.0, s_hi = 1e300;
     if constexpr (VIEW) clip_range(op, o, d, s_lo, s_hi);
     if (ray_setup(tr, o, d, r, s_lo, s_hi)) {
-        FwdSampler<T, K, VEC, NL, VIEW> smp;
+        using Smp = std::conditional_t<V == PO_FWD_CB, CbSampler<K, VEC, NL>, FwdSampler<T, K, VEC, NL, VIEW>>;
+        Smp smp;
         smp.sig = raw_rsrc(tr.sigma, tr.sigma_bytes);
         smp.shb = raw_rsrc(tr.sh, tr.sh_bytes);
         smp.sig_end = tr.sigma_bytes;
         smp.sh_end = tr.sh_bytes;
         smp.rec_bytes = (uint32_t)tr.stride * (uint32_t)sizeof(T);
         smp.stopT = op.stop_T;
-        if constexpr (V == PO_FWD_SH)
+        if constexpr (V == PO_FWD_CB) {
+            smp.cb_basis_bytes = (uint32_t)tr.cb_entries * 8u;
+            smp.cb = raw_rsrc(tr.codebook, (uint32_t)K * smp.cb_basis_bytes);
+        }
+        if constexpr (V == PO_FWD_SH || V == PO_FWD_CB)
             sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], smp.Y);
         else if constexpr (V == PO_FWD_SG)
             sg_basis<K>(tr.lobes, r.dn[0], r.dn[1], r.dn[2], smp.Y);
@@ -899,6 +961,20 @@ bool use_fast(const po_tree* t) {
            ((size_t)t->stride * sizeof(T)) % P::FAST_VEC == 0;
 }
 
+// Load plan of codebook records: K 16-bit positions.
+template <int K>
+struct CbPlan {
+    static constexpr int FAST_VEC = (2 * K) % 16 == 0 ? 16 : 8;
+    static constexpr int FAST_NL = ((2 * K + FAST_VEC - 1) / FAST_VEC) * FAST_VEC / 2;
+    static constexpr int GEN_NL = (K + 1) / 2 * 2;
+};
+
+template <int K>
+bool use_fast_cb(const po_tree* t) {
+    using P = CbPlan<K>;
+    return t->vec_bytes >= P::FAST_VEC && t->stride >= P::FAST_NL && ((size_t)t->stride * 2) % P::FAST_VEC == 0;
+}
+
 template <typename T, int K>
 hipError_t rays_t(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op, float* rgb,
                   float* aux, hipStream_t s) {
@@ -909,6 +985,18 @@ hipError_t rays_t(const po_tree* t, int64_t n, const float* o, const float* d, c
     const bool fast = use_fast<T, K>(t);
     const int v = po_fwd_variant(op, aux, t->kt);
     if (v != PO_FWD_VIEW) aux = nullptr;
+    if constexpr (std::is_same_v<T, __half>) {
+        if (v == PO_FWD_CB) {
+            using Q = CbPlan<K>;
+            if (use_fast_cb<K>(t))
+                hipLaunchKernelGGL((k_render_rays<T, K, Q::FAST_VEC, Q::FAST_NL, PO_FWD_CB>), grid, block, lds, s,
+                                   t->kt, n, nb, o, d, op, rgb, nullptr);
+            else
+                hipLaunchKernelGGL((k_render_rays<T, K, 4, Q::GEN_NL, PO_FWD_CB>), grid, block, lds, s, t->kt, n, nb,
+                                   o, d, op, rgb, nullptr);
+            return hipGetLastError();
+        }
+    }
 #define PO_RAYS(V_)                                                                                              \
     do {                                                                                                        \
         if (fast)                                                                                               \
@@ -940,6 +1028,17 @@ hipError_t camera_t(const po_tree* t, int n_jobs, KJob* jobs, int n_blocks, int 
     for (int j = 0; j < n_jobs; ++j) depth = max(depth, jobs[j].tr.depth);
     dim3 grid((unsigned)grid_for(n_blocks)), block(kBlock);
     const size_t lds = stack_bytes(depth);
+    if constexpr (std::is_same_v<T, __half>) {
+        if (variant == PO_FWD_CB) {
+            using Q = CbPlan<K>;
+            if (use_fast_cb<K>(t))
+                hipLaunchKernelGGL((k_render_camera<T, K, Q::FAST_VEC, Q::FAST_NL, MAXJ, PO_FWD_CB>), grid, block, lds,
+                                   s, B);
+            else
+                hipLaunchKernelGGL((k_render_camera<T, K, 4, Q::GEN_NL, MAXJ, PO_FWD_CB>), grid, block, lds, s, B);
+            return hipGetLastError();
+        }
+    }
     const bool fast = use_fast<T, K>(t);
 #define PO_CAM(V_)                                                                                               \
     do {                                                                                                        \
@@ -1069,21 +1168,20 @@ hipError_t po_reset_device_errors() {
 }
 
 int po_plan_id(const po_tree* t) {
+    // record kind (float32, float16, codebook), K and the load plan
+    const int kind = t->codebook ? 2 : (t->desc.dtype == PO_F32 ? 0 : 1);
     bool fast = false;
-    if (t->desc.dtype == PO_F32) {
-        switch (t->K) {
-            case 1: fast = use_fast<float, 1>(t); break;
-            case 4: fast = use_fast<float, 4>(t); break;
-            case 9: fast = use_fast<float, 9>(t); break;
-            case 16: fast = use_fast<float, 16>(t); break;
-        }
-    } else {
-        switch (t->K) {
-            case 1: fast = use_fast<__half, 1>(t); break;
-            case 4: fast = use_fast<__half, 4>(t); break;
-            case 9: fast = use_fast<__half, 9>(t); break;
-            case 16: fast = use_fast<__half, 16>(t); break;
-        }
+    switch (t->K) {
+#define PO_PLAN_CASE(KK)                                                                                    \
+    case KK:                                                                                                \
+        fast = kind == 2 ? use_fast_cb<KK>(t) : (kind == 0 ? use_fast<float, KK>(t) : use_fast<__half, KK>(t)); \
+        break;
+        PO_PLAN_CASE(1)
+        PO_PLAN_CASE(4)
+        PO_PLAN_CASE(9)
+        PO_PLAN_CASE(16)
+        PO_PLAN_CASE(25)
+#undef PO_PLAN_CASE
     }
-    return (t->desc.dtype * 64 + t->K) * 2 + (fast ? 1 : 0);
+    return (kind * 64 + t->K) * 2 + (fast ? 1 : 0);
 }

@@ -18,6 +18,29 @@ def default_stride(sh_degree: int) -> int:
     return (3 * n_coef(sh_degree) + 3) // 4 * 4
 
 
+def codebook_stride(sh_degree: int) -> int:
+    """Index record stride of codebook trees: K rounded up to a multiple of 4."""
+    return (n_coef(sh_degree) + 3) // 4 * 4
+
+
+def codebook_build(sh, M: int = 65536, index_stride=None):
+    """Median-cut codebooks of leaf coefficients sh (n, 3, K) (po_codebook_build).
+
+    Returns (codebook (K, M, 4) uint16 float16 bits, index (n, stride) uint16,
+    boxes (K,) int32 colours used per basis function)."""
+    sh = np.ascontiguousarray(np.asarray(sh, np.float32))
+    n, three, K = sh.shape
+    if three != 3:
+        raise ValueError("sh must be (n, 3, K)")
+    stride = (K + 3) // 4 * 4 if index_stride is None else int(index_stride)
+    cb = np.zeros((K, int(M), 4), np.uint16)
+    idx = np.zeros((n, stride), np.uint16)
+    boxes = np.zeros(K, np.int32)
+    L.call("po_codebook_build", n, K, sh.ctypes.data if n else None, 3 * K, int(M), cb.ctypes.data,
+           idx.ctypes.data if n else None, stride, boxes.ctypes.data)
+    return cb, idx, boxes
+
+
 def make_desc(depth, sh_degree, center=(0.0, 0.0, 0.0), half=1.0, dtype=L.PO_F32, sh_stride=0) -> L.po_tree_desc:
     d = L.po_tree_desc()
     d.depth = int(depth)
@@ -75,7 +98,7 @@ class Tree:
     handle.  The handle borrows the tensors; this object keeps them alive."""
 
     def __init__(self, depth, sh_degree, child, sigma, sh, center=(0.0, 0.0, 0.0), half=1.0, perm=None,
-                 lobes=None):
+                 lobes=None, codebook=None):
         import torch
 
         self.depth, self.sh_degree = int(depth), int(sh_degree)
@@ -87,7 +110,11 @@ class Tree:
             self.dtype = L.PO_F16
         else:
             raise TypeError("sigma must be float32 or float16")
-        if sh.dtype != sigma.dtype:
+        if codebook is not None:
+            # codebook tree: sh holds the 16-bit positions (int16 storage), codebook (K, M, 4) float16
+            if sigma.dtype != torch.float16 or sh.dtype != torch.int16:
+                raise TypeError("codebook trees take float16 sigma and int16 (16-bit position) records")
+        elif sh.dtype != sigma.dtype:
             raise TypeError("sigma and sh must share a dtype")
         if child.dtype != torch.int32 or child.dim() != 2 or child.shape[1] != 8:
             raise TypeError("child must be an int32 (n_nodes, 8) tensor")
@@ -95,16 +122,24 @@ class Tree:
             if not t.is_cuda or not t.is_contiguous():
                 raise ValueError("tree arrays must be contiguous device tensors")
         self.n_leaves = int(sigma.shape[0])
-        if sh.dim() != 2 or sh.shape[0] != self.n_leaves or sh.shape[1] < 3 * self.K:
-            raise ValueError(f"sh must be (n_leaves, stride >= {3 * self.K})")
+        rec_min = self.K if codebook is not None else 3 * self.K
+        if sh.dim() != 2 or sh.shape[0] != self.n_leaves or sh.shape[1] < rec_min:
+            raise ValueError(f"sh must be (n_leaves, stride >= {rec_min})")
         self.stride = int(sh.shape[1])
         self.child, self.sigma, self.sh = child, sigma, sh
         self.perm = perm
         self.lobes = lobes
+        self.codebook = codebook
         self.desc = make_desc(depth, sh_degree, center, half, self.dtype, self.stride)
         h = ctypes.c_void_p()
         leaf_ptrs = (sigma.data_ptr() if self.n_leaves else None, sh.data_ptr() if self.n_leaves else None)
-        if lobes is None:
+        if codebook is not None:
+            if not (codebook.is_cuda and codebook.dtype == torch.float16 and codebook.dim() == 3
+                    and codebook.shape[0] == self.K and codebook.shape[2] == 4 and codebook.is_contiguous()):
+                raise ValueError(f"codebook must be a contiguous float16 ({self.K}, M, 4) device tensor")
+            L.call("po_tree_bind_codebook", ctypes.byref(self.desc), int(child.shape[0]), child.data_ptr(),
+                   self.n_leaves, *leaf_ptrs, codebook.data_ptr(), int(codebook.shape[1]), ctypes.byref(h))
+        elif lobes is None:
             L.call("po_tree_bind", ctypes.byref(self.desc), int(child.shape[0]), child.data_ptr(), self.n_leaves,
                    *leaf_ptrs, ctypes.byref(h))
         else:
@@ -125,7 +160,8 @@ class Tree:
         return int(self.child.shape[0])
 
     def nbytes(self) -> int:
-        return sum(int(t.numel() * t.element_size()) for t in (self.child, self.sigma, self.sh))
+        arrays = [self.child, self.sigma, self.sh] + [t for t in (self.lobes, self.codebook) if t is not None]
+        return sum(int(t.numel() * t.element_size()) for t in arrays)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -171,10 +207,39 @@ class Tree:
                               scene["center"], scene["half"], dtype=dtype, device=device, stride=stride,
                               lobes=scene.get("lobes"))
 
+    @classmethod
+    def from_cells_codebook(cls, depth, sh_degree, cells, sigma, sh, M=65536, center=(0.0, 0.0, 0.0), half=1.0,
+                            device="cuda", index_stride=None):
+        """Codebook tree (App. B.2): the coefficients are median-cut per basis
+        function in the caller's cell order (po_codebook_build), the densities
+        kept as float16; records hold 16-bit codebook positions."""
+        import torch
+
+        cells = np.asarray(cells, np.int32).reshape(-1, 4)
+        n = cells.shape[0]
+        K = n_coef(sh_degree)
+        child, perm = build_host(depth, sh_degree, cells, center, half)
+        sig = np.asarray(sigma, np.float32).reshape(n)
+        if np.abs(sig).max(initial=0) > 65504:
+            raise ValueError("densities exceed the float16 range")
+        cb, idx, _ = codebook_build(np.asarray(sh, np.float32).reshape(n, 3, K), M, index_stride)
+        dev = torch.device(device)
+        t_child = torch.from_numpy(child).to(dev)
+        t_sig = torch.from_numpy(np.ascontiguousarray(sig[perm].astype(np.float16))).to(dev)
+        t_idx = torch.from_numpy(np.ascontiguousarray(idx[perm]).view(np.int16)).to(dev)
+        t_cb = torch.from_numpy(cb.view(np.float16)).to(dev)
+        return cls(depth, sh_degree, t_child, t_sig, t_idx, center, half, perm=perm, codebook=t_cb)
+
     def leaf_values(self):
-        """(sigma (n,), sh (n, 3, K)) as float32 NumPy arrays in the caller's cell order."""
+        """(sigma (n,), sh (n, 3, K)) as float32 NumPy arrays in the caller's cell
+        order (codebook trees: the decoded coefficients)."""
         sig = self.sigma.float().cpu().numpy()
-        sh = self.sh[:, :3 * self.K].float().cpu().numpy().reshape(-1, 3, self.K)
+        if self.codebook is not None:
+            pos = self.sh[:, :self.K].cpu().numpy().view(np.uint16).astype(np.int64)
+            cb = self.codebook.float().cpu().numpy()
+            sh = np.stack([cb[k][pos[:, k], :3] for k in range(self.K)], axis=2)
+        else:
+            sh = self.sh[:, :3 * self.K].float().cpu().numpy().reshape(-1, 3, self.K)
         if self.perm is None:
             return sig, sh
         inv = np.empty_like(self.perm)

@@ -261,3 +261,35 @@ def test_leaf_cells_recover_the_builder_input(lib, seed, depth):
     bad[0, 0] = ch.shape[0] + 5
     st = lib.po_tree_leaf_cells(ctypes.byref(desc), bad.shape[0], bad.ctypes.data, n, out.ctypes.data)
     assert st == L.PO_ERR_TREE
+
+
+def test_codebook_bind_and_render_errors(lib):
+    fake = 0x10000
+    d16 = make_desc(5, 2, dtype=L.PO_F16)
+    h = ctypes.c_void_p()
+    # codebook trees need float16 densities, an even index stride >= K and 1..65536 aligned entries
+    d32 = make_desc(5, 2)
+    assert lib.po_tree_bind_codebook(ctypes.byref(d32), 10, fake, 20, fake, fake, fake, 256, ctypes.byref(h)) == L.PO_ERR_INVALID
+    assert lib.po_tree_bind_codebook(ctypes.byref(d16), 10, fake, 20, fake, fake, fake, 0, ctypes.byref(h)) == L.PO_ERR_INVALID
+    assert lib.po_tree_bind_codebook(ctypes.byref(d16), 10, fake, 20, fake, fake, fake, 65537, ctypes.byref(h)) == L.PO_ERR_INVALID
+    assert lib.po_tree_bind_codebook(ctypes.byref(d16), 10, fake, 20, fake, fake, fake + 4, 16, ctypes.byref(h)) == L.PO_ERR_INVALID
+    assert lib.po_tree_bind_codebook(ctypes.byref(d16), 10, fake, 20, fake, fake, None, 16, ctypes.byref(h)) == L.PO_ERR_INVALID
+    odd = make_desc(5, 2, dtype=L.PO_F16, sh_stride=11)
+    assert lib.po_tree_bind_codebook(ctypes.byref(odd), 10, fake, 20, fake, fake, fake, 16, ctypes.byref(h)) == L.PO_ERR_INVALID
+    short = make_desc(5, 2, dtype=L.PO_F16, sh_stride=8)
+    assert lib.po_tree_bind_codebook(ctypes.byref(short), 10, fake, 20, fake, fake, fake, 16, ctypes.byref(h)) == L.PO_ERR_INVALID
+    L.call("po_tree_bind_codebook", ctypes.byref(d16), 10, fake, 20, fake, fake, fake, 16, ctypes.byref(h))
+    opts = L.po_render_opts()
+    opts.stop_T = 1e-4
+    # no viewer outputs and no gradients for codebook trees
+    opts.flags = L.PO_OUT_AUX
+    assert lib.po_render_rays(h, 5, fake, fake, ctypes.byref(opts), fake, fake, None) == L.PO_ERR_UNSUPPORTED
+    opts.flags = 0
+    opts.sh_off = 1
+    cam = L.po_camera()
+    cam.width, cam.height, cam.fx, cam.fy = 8, 8, 1.0, 1.0
+    assert lib.po_render_camera(h, ctypes.byref(cam), ctypes.byref(opts), fake, None, None) == L.PO_ERR_UNSUPPORTED
+    opts.sh_off = 0
+    st = lib.po_render_rays_backward(h, 5, fake, fake, ctypes.byref(opts), fake, fake, fake, fake, None)
+    assert st == L.PO_ERR_UNSUPPORTED
+    lib.po_tree_destroy(h)
