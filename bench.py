@@ -11,7 +11,9 @@ the device.
 
 Prints one JSON line: FPS of the float32 tree (headline value), Msamples/s,
 the float16-leaf form, a roofline entry for the render kernel and the FP64
-oracle's throughput on the host cores as the CPU baseline.
+oracle's throughput on the host cores as the CPU baseline.  Further legs: the
+optimisation step (differentiation), serving, the viewer outputs, the
+visibility filter, the colour-basis sweep and codebook leaves.
 """
 from __future__ import annotations
 
@@ -257,6 +259,41 @@ def basis_leg(po, scenes, scene, cams, frames=50):
                               "hardware": "Tesla V100", "workload": "NeRF-synthetic real scenes"}}
 
 
+def codebook_leg(po, scene, cams, frames=50, M=65536):
+    """Codebook leaves (App. B.2) on the main workload: median-cut codebooks of
+    2^16 float16 colours per basis function built on the host, 16-bit
+    positions per leaf, float16 densities; render FPS, and the colour error
+    of the compressed tree against the float32 tree's render of the same
+    poses (quantisation error)."""
+    import numpy as np
+    import torch
+
+    t0 = time.perf_counter()
+    tree = po.Tree.from_cells_codebook(scene["depth"], scene["sh_degree"], scene["cells"], scene["sigma"],
+                                       scene["sh"], M, scene["center"], scene["half"])
+    t_build = time.perf_counter() - t0
+    ms = _time_frames(po, tree, cams, frames)
+    ref = po.Tree.from_scene(scene, dtype="f32")
+    err_max, se, n = 0.0, 0.0, 0
+    for c in cams[:4]:
+        a = po.render_camera(ref, c, stop_T=STOP_T)
+        b = po.render_camera(tree, c, stop_T=STOP_T)
+        e = (a - b).abs()
+        err_max = max(err_max, float(e.max()))
+        se += float((e * e).sum())
+        n += e.numel()
+    mse = se / n
+    rec = 2 + 2 * tree.K
+    out = {"workload": "depth-9 blob band, SH-16, %d-entry float16 codebook per basis function" % M,
+           "fps": round(1e3 / ms, 1), "build_s": round(t_build, 1),
+           "leaf_bytes": rec, "leaf_bytes_f16": 2 * (1 + 3 * tree.K), "leaf_bytes_f32": 4 * (1 + 3 * tree.K),
+           "codebook_mb": round(tree.codebook.numel() * 2 / 1e6, 1), "tree_mb": round(tree.nbytes() / 1e6, 1),
+           "err_vs_f32_max": round(err_max, 5), "psnr_vs_f32": round(float(10 * np.log10(1.0 / max(mse, 1e-30))), 2)}
+    del tree, ref
+    torch.cuda.empty_cache()
+    return out
+
+
 def view_leg(po, tree, cams, frames=50):
     """Viewer outputs (Sec. 5.5) on the main workload: cost of the depth and
     alpha maps (aux output), of an SH subset and of a slicing plane relative
@@ -410,6 +447,8 @@ def main():
         del tree16
     if not args.no_extra:
         out["basis"] = basis_leg(po, scenes, scene, cams)
+        out["codebook"] = codebook_leg(po, scene, cams)
+        log(f"codebook: {out['codebook']}")
     if not args.no_train:
         log("differentiation: direct octree optimisation")
         out["train"] = train_leg(po, scenes)
