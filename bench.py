@@ -5,9 +5,12 @@ Workload: the depth-9 Gaussian-blob surface-band tree (~2.9M leaves, SH
 degree 3, sigma ~ lognormal(2, 1), SH ~ N(0, 0.5^2)), 200 camera poses
 area-uniform on the upper hemisphere at radius 4 looking at the origin,
 800x800 pixels, 40 degree horizontal field of view, white background, early
-stop at T < 1e-4.  A step is one 800x800 frame: one kernel launch over all
-640,000 rays.  Inputs are resident in HBM before timing; the image stays on
-the device.
+stop at T < 1e-4.  A step is one 800x800 frame: one render_camera call over
+all 640,000 rays, i.e. the render pass of five launches (the walk of every
+ray, the chunks and sub-chunks of the long walks, the join, and the clearing
+of the queue counters).  Inputs are resident in HBM before timing; the image
+stays on the device.  The one-pass render of the same frames (one launch,
+every ray walked to its end by one lane) is timed beside it.
 
 Prints one JSON line: FPS of the float32 tree (headline value), Msamples/s,
 the float16-leaf form, a roofline entry for the render kernel and the FP64
@@ -45,9 +48,10 @@ def kernel_hash() -> str:
 
 
 def counter_traffic(dtype: str):
-    """HBM bytes per launch of the float32/float16 render kernel from the
-    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, scaled by
-    a plain copy), or None when the kernel source changed since."""
+    """HBM bytes per frame of the float32/float16 render pass (its five
+    launches) from the committed rocprofv3 counter summary (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy), or None when the kernel source
+    changed since."""
     try:
         with open(TRAFFIC_PROFILE) as f:
             text = f.read()
@@ -58,8 +62,8 @@ def counter_traffic(dtype: str):
     h = re.search(r"kernel_source_sha256_16 = `([0-9a-f]+)`", text)
     if h is None or h.group(1) != kernel_hash():
         return None
-    vals = dict(re.findall(r"(hbm_bytes_per_launch_f(?:16|32)) = `(\d+)`", text))
-    v = vals.get("hbm_bytes_per_launch_" + dtype)
+    vals = dict(re.findall(r"(hbm_bytes_per_frame_f(?:16|32)) = `(\d+)`", text))
+    v = vals.get("hbm_bytes_per_frame_" + dtype)
     return float(v) if v else None
 
 
@@ -111,6 +115,27 @@ def measure(po, tree, cams, steps, warmup, stream, aux_pass=True):
                 mrays_per_s=rays / (ms * 1e3), samples_per_ray=n_samples / rays, steps_per_ray=n_steps / rays,
                 alg_gbps=alg_bytes / (ms * 1e-3) / 1e9, alg_bytes_per_launch=alg_bytes / steps,
                 lane_efficiency=lane_eff)
+
+
+def measure_one_pass(po, tree, cams, steps, warmup, stream):
+    """The same frames rendered in one pass (a single-job batch: one launch,
+    one lane per ray walking it to its end)."""
+    import torch
+
+    img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    jobs = [[po.Job(tree, cam, img, stop_T=STOP_T)] for cam in cams]
+    for i in range(warmup):
+        po.render_batch(jobs[i % len(cams)], stream=stream)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        t0.record(stream)
+        for i in range(steps):
+            po.render_batch(jobs[i % len(cams)], stream=stream)
+        t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    return {"fps": round(steps / (ms * 1e-3), 2), "ms_per_step": round(ms / steps, 4)}
 
 
 def cpu_baseline(scene, poses, budget_s=12.0):
@@ -408,6 +433,8 @@ def main():
     log(f"fp32: {r32['fps']:.1f} FPS, {r32['msamples_per_s']:.0f} Msamples/s, "
         f"{r32['samples_per_ray']:.2f} samples/ray, {r32['steps_per_ray']:.1f} steps/ray, "
         f"lane efficiency {r32['lane_efficiency']:.3f}")
+    one32 = measure_one_pass(po, tree32, cams, args.steps, args.warmup, stream)
+    log(f"fp32 one pass: {one32['fps']:.1f} FPS")
     tb = counter_traffic("f32")
     traffic_gbps = None if tb is None else round(tb / (r32["ms_per_step"] * 1e-3) / 1e9, 1)
     out = {
@@ -420,11 +447,13 @@ def main():
         "msamples_per_s": round(r32["msamples_per_s"], 1), "mrays_per_s": round(r32["mrays_per_s"], 1),
         "samples_per_ray": round(r32["samples_per_ray"], 3), "steps_per_ray": round(r32["steps_per_ray"], 2),
         "lane_efficiency": round(r32["lane_efficiency"], 4),
+        "one_pass": one32,
         "roofline": {"bound": "hbm", "achieved": round(r32["alg_gbps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(r32["alg_gbps"] / HBM_PEAK_GBPS, 4), "traffic": traffic_gbps,
-                     "kernel": "k_render_camera<float,16,16,48,1,0>",
-                     "alg_bytes_per_launch": int(r32["alg_bytes_per_launch"]),
-                     "hbm_bytes_per_launch": None if tb is None else int(tb)},
+                     "kernel": "render pass <float,16,16,48,SH>: k_zero_i32, k_render_camera_split, "
+                               "k_render_chunks, k_render_subchunks, k_render_join",
+                     "alg_bytes_per_frame": int(r32["alg_bytes_per_launch"]),
+                     "hbm_bytes_per_frame": None if tb is None else int(tb)},
         "paper_context": {"fps": 167.68, "hardware": "Tesla V100", "workload": "NeRF-synthetic real scenes"},
     }
     if not args.no_extra:
@@ -438,12 +467,13 @@ def main():
         tree16 = po.Tree.from_scene(scene, dtype="f16")
         r16 = measure(po, tree16, cams, args.steps, args.warmup, stream)
         log(f"fp16: {r16['fps']:.1f} FPS, {r16['msamples_per_s']:.0f} Msamples/s")
+        one16 = measure_one_pass(po, tree16, cams, args.steps, args.warmup, stream)
         t16 = counter_traffic("f16")
         out["fp16"] = {"fps": round(r16["fps"], 2), "ms_per_step": round(r16["ms_per_step"], 4),
                        "msamples_per_s": round(r16["msamples_per_s"], 1),
                        "alg_gbps": round(r16["alg_gbps"], 1), "alg_frac": round(r16["alg_gbps"] / HBM_PEAK_GBPS, 4),
                        "hbm_gbps": None if t16 is None else round(t16 / (r16["ms_per_step"] * 1e-3) / 1e9, 1),
-                       "speedup_vs_fp32": round(r16["fps"] / r32["fps"], 3)}
+                       "speedup_vs_fp32": round(r16["fps"] / r32["fps"], 3), "one_pass": one16}
         del tree16
     if not args.no_extra:
         out["basis"] = basis_leg(po, scenes, scene, cams)

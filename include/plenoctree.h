@@ -208,7 +208,20 @@ po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, co
 
 /* po_render_camera: renders a camera image into d_rgb[height][width][3]
  * (and d_aux[height][width][4] with PO_OUT_AUX).  width, height in
- * [1, 16384]; fx, fy non-zero.  Errors as for po_render_rays. */
+ * [1, 16384]; fx, fy non-zero.
+ * Images of at least 65536 pixels without viewer options are rendered in
+ * pieces: every ray is walked for a bounded number of cells, the rays with
+ * cells left are cut into parameter intervals walked in parallel, and the
+ * pieces are composited front to back (compositing is associative, Sec. 3
+ * eqn:quad), the piece holding the early stop walked again with the known
+ * transmittance.  The colour equals the one-pass render (po_render_batch)
+ * up to float rounding; where T lands within rounding of stop_T the two can
+ * stop one cell apart, which moves at most stop_T of weight.  For this the
+ * library keeps a work queue of about 300 MB per (device, stream), made on
+ * the first such call and held until the process ends (if it cannot be
+ * allocated, the image is rendered in one pass).  Calls on one stream are
+ * ordered; calls on different streams use different queues.  Errors as for
+ * po_render_rays. */
 po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_render_opts* opts,
                            float* d_rgb, float* d_aux, void* stream);
 

@@ -10,8 +10,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "po_internal.h"
@@ -40,6 +43,50 @@ po_status device_fail(hipError_t e, const char* what) {
 }
 
 bool finite(float v) { return std::isfinite(v); }
+
+// Camera renders of at least this many pixels use the split render.
+constexpr int64_t kSplitMinPixels = 1 << 16;
+
+// Work queues of the split camera render, one per (device, stream), made on
+// first use and kept until the process ends.
+std::mutex g_split_mu;
+std::map<std::pair<int, void*>, void*> g_split;
+
+bool split_queue(void* stream, KSplit* S) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_split_mu);
+        auto it = g_split.find({dev, stream});
+        if (it != g_split.end()) {
+            base = it->second;
+        } else {
+            if (hipMalloc(&base, kSplitBytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return false;
+            }
+            g_split[{dev, stream}] = base;
+        }
+    }
+    char* p = static_cast<char*>(base);
+    const size_t n = (size_t)kSplitSlots;
+    S->count = reinterpret_cast<int32_t*>(p);
+    S->count2 = S->count + kSplitRegions;
+    p += 512;
+    S->info = reinterpret_cast<int32_t*>(p);
+    S->head = p + n * 8;
+    S->part = p + n * 40;
+    p += n * 72;
+    S->info2 = reinterpret_cast<int32_t*>(p);
+    S->head2 = p + n * 8;
+    S->part2 = p + n * 40;
+    S->split_steps = PO_SPLIT_STEPS;
+    S->chunk_steps = PO_CHUNK_STEPS;
+    S->chunk_cap = PO_CHUNK_CAP;
+    S->ub_frac = PO_SPLIT_UB_FRAC;
+    return true;
+}
 
 }  // namespace
 
@@ -499,8 +546,15 @@ po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_rend
     j.tile_begin = 0;
     j.block_begin = 0;
     j.tiles_x = (cam->width + PO_TILE - 1) / PO_TILE;
-    hipError_t e = po_launch_camera_jobs(t, 1, &j, 4 * tiles_of(cam), po_fwd_variant(j.op, j.aux, t->kt),
-                                         (hipStream_t)stream);
+    const int variant = po_fwd_variant(j.op, j.aux, t->kt);
+    const bool plain = variant == PO_FWD_SH || variant == PO_FWD_SG;
+    KSplit S;
+    hipError_t e;
+    if (plain && (int64_t)cam->width * cam->height >= kSplitMinPixels && j.op.max_steps > PO_SPLIT_STEPS &&
+        split_queue(stream, &S))
+        e = po_launch_camera_split(t, j, 4 * tiles_of(cam), variant, S, (hipStream_t)stream);
+    else
+        e = po_launch_camera_jobs(t, 1, &j, 4 * tiles_of(cam), variant, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "render_camera launch");
     return ok();
 }

@@ -72,6 +72,46 @@ struct KJob {
     int32_t pad_;
 };
 
+// Work queues of the split camera render: rays whose walk outlasts
+// split_steps cells are handed on as 1-16 chunks, and chunks that outlast
+// chunk_cap cells hand their remainder on as 1-16 sub-chunks.  Each queue has
+// kSplitRegions regions of kSplitRegionSlots slots, one counter each.
+#ifndef PO_SPLIT_REGION_SLOTS
+#define PO_SPLIT_REGION_SLOTS 32768
+#endif
+constexpr int kSplitRegions = 64;
+constexpr int kSplitRegionSlots = PO_SPLIT_REGION_SLOTS;
+constexpr int kSplitSlots = kSplitRegions * kSplitRegionSlots;
+constexpr int kSplitMaxChunks = 16;
+#ifndef PO_SPLIT_STEPS
+#define PO_SPLIT_STEPS 32
+#endif
+#ifndef PO_CHUNK_STEPS
+#define PO_CHUNK_STEPS 32
+#endif
+#ifndef PO_CHUNK_CAP
+#define PO_CHUNK_CAP 24
+#endif
+#ifndef PO_SPLIT_UB_FRAC
+#define PO_SPLIT_UB_FRAC 0.2f
+#endif
+struct KSplit {
+    int32_t* count;        // [kSplitRegions] chunk slots claimed (may exceed the region); count2 follows
+    int32_t* count2;       // [kSplitRegions] sub-chunk slots claimed
+    int32_t* info;         // [kSplitSlots][2] first slot of the ray (-1: unused), chunk | chunk count << 8
+    void* head;            // [kSplitSlots] 32-byte ray states, at the first slot of each ray
+    void* part;            // [kSplitSlots] 32-byte chunk results
+    int32_t* info2;        // [kSplitSlots][2] first slot of the remainder (-1: unused), piece | count << 8
+    void* head2;           // [kSplitSlots] 32-byte remainders, at their first slot
+    void* part2;           // [kSplitSlots] 32-byte sub-chunk results
+    int32_t split_steps;   // cells walked before a ray is handed on
+    int32_t chunk_steps;   // target cells per chunk
+    int32_t chunk_cap;     // cells a chunk walks before its remainder is handed on
+    float ub_frac;         // pieces cover at least this fraction of the finest-cell faces ahead
+};
+// Device bytes of the queues (counters, then info, head, part of each).
+constexpr size_t kSplitBytes = 512 + 2 * (size_t)kSplitSlots * (8 + 32 + 32);
+
 struct po_tree {
     po_tree_desc desc;
     int64_t n_nodes, n_leaves;
@@ -99,6 +139,11 @@ hipError_t po_launch_backward(const po_tree* t, int64_t n, const float* o, const
 // workgroups, four per 16x16 tile.
 hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, int variant,
                                  hipStream_t s);
+// One camera job as the split render (plain SH or SG variants of float32 or
+// float16 trees): clears the queue counters and launches the three kernels.
+// The queue must not be in use by work on another stream.
+hipError_t po_launch_camera_split(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
+                                  hipStream_t s);
 hipError_t po_launch_camera_rays(const KCam& cam, float* o, float* d, hipStream_t s);
 // Visibility filter: mode 0 alpha, 1 contribution; weight[n_leaves] raised in place, alpha[H*W] or nullptr.
 hipError_t po_launch_leaf_weights(const po_tree* t, const KCam& cam, const KOpts& op, int mode, float* weight,

@@ -230,6 +230,8 @@ struct Ray {
     int c[3];      // finest-level coordinates of the current cell
     double s;      // current parameter
     double s_end;  // end of the rendered part (slicing plane), else 1e300
+    double s_exit; // end of the walk: min(s_end, box exit)
+    bool more;     // split walks: the walk stopped at its step limit with cells left
 };
 
 // The walk covers the parameters s in [max(s_lo, 0), s_hi] inside the box.
@@ -267,6 +269,7 @@ __device__ __forceinline__ bool ray_setup(const KTree& tr, const double (&o)[3],
     }
     r.s = s0;
     r.s_end = s_hi;
+    r.s_exit = s1;
     return true;
 }
 
@@ -314,7 +317,18 @@ __device__ __forceinline__ uint32_t child_slot(const int (&c)[3], int D, int L) 
 // buffer descriptor: an entry beyond the array reads as 0 (empty), and an
 // internal entry below depth D or past the node count is counted as
 // malformed and taken as empty.
-template <class Sampler>
+//
+// SPLIT: reaching max_steps with cells left is not an error; the walk then
+// leaves r.s and r.c at the start of the next cell and sets r.more (unless
+// the last sample ended it by early stopping), so that it can be resumed or
+// handed on.  A chunk sampler (kChunk) learns for every sample whether its
+// cell ends inside the walked range (cpl_next) or is cut by r.s_end.
+template <class S, class = void>
+struct is_chunk : std::false_type {};
+template <class S>
+struct is_chunk<S, std::void_t<decltype(S::kChunk)>> : std::bool_constant<S::kChunk> {};
+
+template <class Sampler, bool SPLIT = false>
 __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int* __restrict__ stk,
                                      Sampler& smp) {
     const int D = tr.depth;
@@ -322,7 +336,7 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
     const uint32_t tr_child_end = (uint32_t)tr.n_nodes * 32u;
     const __amdgpu_buffer_rsrc_t child = raw_rsrc(tr.child, tr_child_end);
     int steps = 0;
-    bool pending = false, bad = false;
+    bool pending = false, bad = false, cap_end = false;
     int L = 0, node = 0;
     stk[0] = 0;
     int e = __builtin_amdgcn_raw_buffer_load_b32(child, child_slot(r.c, D, 0) << 2, 0, 0);
@@ -366,7 +380,11 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
             sk[k] = ((double)(lo[k] + (pos[k] ? csz : 0)) - r.og[k]) * r.inv[k];
         }
         double se = fmax(fmin(fmin(sk[0], sk[1]), sk[2]), r.s);
-        if constexpr (Sampler::kClip) se = fmin(se, r.s_end);
+        bool cpl = true;
+        if constexpr (Sampler::kClip) {
+            cpl = se <= r.s_end;
+            se = fmin(se, r.s_end);
+        }
         const float delta = (float)((se - r.s) * r.len);
         const float t_in = (float)(r.s * r.len);
         ++steps;
@@ -388,7 +406,7 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
         if constexpr (Sampler::kClip) out |= se >= r.s_end;
         r.s = se;
         const bool capped = !out & (steps >= max_steps);
-        bad |= capped;
+        if constexpr (!SPLIT) bad |= capped;
         const bool last = out | capped;
         // prefetch the next cell's entry, from the deepest common ancestor: the
         // cells agree on the coordinate bits above the highest differing one.
@@ -404,6 +422,13 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
             r.c[2] = nc[2];
             pf = ((uint32_t)node << 5) | (child_slot(r.c, D, L) << 2);
         }
+        if constexpr (SPLIT) {
+            if (capped) {
+                r.c[0] = nc[0];
+                r.c[1] = nc[1];
+                r.c[2] = nc[2];
+            }
+        }
         e = __builtin_amdgcn_raw_buffer_load_b32(child, pf, 0, 0);
         // composite the previous sample (its loads precede the prefetch)
         bool stop = false;
@@ -416,12 +441,16 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
         // walk ends only at the bottom of the body, so every path back to the
         // top has issued the same loads.
         const bool take = !stop & (leaf >= 0) & (delta > 0.0f);
+        if constexpr (is_chunk<Sampler>::value) smp.cpl_next = cpl;
         smp.issue(take ? leaf : -1, delta, t_in);
         pending = take;
+        if constexpr (SPLIT) cap_end = capped & !stop;
         if (last | stop) break;
     }
-    if (pending) smp.consume();
+    bool end_stop = false;
+    if (pending) end_stop = smp.consume();
     smp.flush();
+    if constexpr (SPLIT) r.more = cap_end & !end_stop;
     // a lane that met a malformed entry or the step cap is counted once
     if (bad) atomicAdd(&g_po_errors, 1ull);
     return steps;
@@ -484,6 +513,38 @@ struct FwdSampler {
         }
         Tl = Tl * ex;
         return Tl < stopT;
+    }
+};
+
+// One chunk [s_lo, s_hi] of a split ray.  The chunk composites from T = 1
+// (or from a known transmittance when it is walked again); because
+// compositing is associative, chunk results combine front to back with the
+// over operator.  Early stopping is tested where the sequential walk tests it,
+// at the end of a cell: a sample whose cell continues past s_hi (cut by the
+// chunk boundary) is composited without a test, and its remainder, the first
+// sample of the next chunk, carries the test.  Tlast is T after the last
+// tested sample (-1: none); the chunk stops itself once T < stopT there,
+// since its walk cannot matter past that point for any transmittance in
+// front of it.
+template <typename T, int K, int VEC, int NL>
+struct ChunkSampler : FwdSampler<T, K, VEC, NL, false> {
+    using Base = FwdSampler<T, K, VEC, NL, false>;
+    static constexpr bool kClip = true;
+    static constexpr bool kChunk = true;
+    bool cpl_next = true, cpl = true;
+    bool hit = false;  // stopped by stopT
+    float Tlast = -1.0f;
+
+    __device__ __forceinline__ void issue(int leaf, float d, float t_in) {
+        Base::issue(leaf, d, t_in);
+        cpl = cpl_next;
+    }
+    __device__ __forceinline__ bool consume() {
+        const bool st = Base::consume();
+        if (!cpl) return false;
+        Tlast = this->Tl;
+        hit |= st;
+        return st;
     }
 };
 
@@ -706,6 +767,388 @@ __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
             J.aux[4 * p + 3] = dep;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Split camera render.  The frame time of a one-pass render is set by its
+// longest walks (a few hundred cells, against a median of a few), which run
+// one cell at a time while most of the chip idles.  Compositing is
+// associative (Sec. 3, eqn:quad: a range of segments acts on what lies behind
+// it as (C, T) -> C_range + T_range C), so a long walk can be cut into
+// pieces walked in parallel and joined front to back:
+//   k_render_camera_split  walks every ray for at most split_steps cells;
+//                          a ray with cells left is handed on: its state
+//                          (s, T, C) and 1-16 chunks, equal parameter
+//                          intervals of the rest of the ray;
+//   k_render_chunks        walks one chunk per lane for at most chunk_cap
+//                          cells; a chunk with cells left hands its
+//                          remainder on as 1-16 sub-chunks (cells are
+//                          bunched along a ray, so equal intervals are not
+//                          equal work; the walked part of the chunk tells
+//                          how dense the rest is);
+//   k_render_subchunks     walks one sub-chunk per lane to its end;
+//   k_render_join          combines each ray's pieces in order and writes
+//                          the pixel.  Where early stopping ends the ray
+//                          inside a piece (T below stop_T after a cell), the
+//                          piece is walked again from its start with the
+//                          known transmittance and stops where the one-pass
+//                          walk stops.
+// The result equals the one-pass render up to float rounding.  The queues
+// are split into regions (one counter each) to spread the slot claims; a
+// walk that finds its region full finishes in the lane that holds it.
+// ---------------------------------------------------------------------------
+struct ContHead {
+    double s;             // parameter where the first walk stopped (start of the next cell)
+    float T, c0, c1, c2;  // transmittance and colour so far
+    int32_t pix;          // pixel index py * W + px
+    int32_t pad;
+};
+static_assert(sizeof(ContHead) == 32, "queue record layout");
+
+struct SubHead {
+    double lo, hi;        // remainder of a chunk: [lo, hi] (hi 1e300: to the box exit)
+    int32_t pix;
+    int32_t pad[3];
+};
+static_assert(sizeof(SubHead) == 32, "queue record layout");
+
+// Result of a walked piece: colour and transmittance composited from T = 1,
+// T after its last tested sample (-1: none), and for a chunk its remainder's
+// sub-chunks (first slot, count; -1 none).
+struct PieceOut {
+    float c0, c1, c2, T;
+    float Tlast;
+    int32_t sub, n_sub, pad;
+};
+static_assert(sizeof(PieceOut) == 32, "queue record layout");
+
+template <typename T, int K, int V, class Smp>
+__device__ __forceinline__ void fwd_init(Smp& smp, const KTree& tr, const KOpts& op, const Ray& r) {
+    smp.sig = raw_rsrc(tr.sigma, tr.sigma_bytes);
+    smp.shb = raw_rsrc(tr.sh, tr.sh_bytes);
+    smp.sig_end = tr.sigma_bytes;
+    smp.sh_end = tr.sh_bytes;
+    smp.rec_bytes = (uint32_t)tr.stride * (uint32_t)sizeof(T);
+    smp.stopT = op.stop_T;
+    if constexpr (V == PO_FWD_SG)
+        sg_basis<K>(tr.lobes, r.dn[0], r.dn[1], r.dn[2], smp.Y);
+    else
+        sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], smp.Y);
+}
+
+// Piece k of n of the parameter range [a, hi] of a pixel's ray: equal
+// intervals of [a, min(hi, box exit)], the last one running to hi itself.
+// Sets up r for the walk of the piece; false when the piece is empty.
+__device__ __forceinline__ bool piece_setup(const KJob& J, int pix, double a, double hi, int k, int n, Ray& r) {
+    double ro[3], rd[3];
+    pixel_ray(J.cam, pix % J.cam.W, pix / J.cam.W, ro, rd);
+    if (!ray_setup(J.tr, ro, rd, r, a, hi)) return false;
+    const double len = r.s_exit - a;
+    const double lo = k == 0 ? a : a + len * (double)k / (double)n;
+    const double up = k + 1 < n ? a + len * (double)(k + 1) / (double)n : hi;
+    return ray_setup(J.tr, ro, rd, r, lo, up);
+}
+
+// Bounds of piece k of n of [a, hi] (as piece_setup cuts it).
+__device__ __forceinline__ void piece_bounds(const KJob& J, int pix, double a, double hi, int k, int n,
+                                             double& lo, double& up) {
+    double ro[3], rd[3];
+    pixel_ray(J.cam, pix % J.cam.W, pix / J.cam.W, ro, rd);
+    Ray r;
+    const double e = ray_setup(J.tr, ro, rd, r, a, hi) ? r.s_exit : a;
+    lo = k == 0 ? a : a + (e - a) * (double)k / (double)n;
+    up = k + 1 < n ? a + (e - a) * (double)(k + 1) / (double)n : hi;
+}
+
+// Pieces wanted for the rest [r.s, r.s_exit] of a walk that crossed `steps`
+// cells since s_first: about chunk_steps cells each, from the cells per unit
+// parameter so far, and at least ub_frac of the finest-cell faces ahead.
+__device__ __forceinline__ int pieces_wanted(const Ray& r, double s_first, int steps, const KSplit& S) {
+    const double rest = r.s_exit - r.s;
+    double est = (double)steps * rest / fmax(r.s - s_first, 1e-300);
+    est = fmax(est, (double)S.ub_frac * rest * (fabs(r.dg[0]) + fabs(r.dg[1]) + fabs(r.dg[2])));
+    return (int)fmin(fmax(ceil(est / (double)S.chunk_steps), 1.0), (double)kSplitMaxChunks);
+}
+
+// One slot claim per wave: returns this lane's first slot in its region
+// (want > 0) from an inclusive prefix sum over the wave.  Every lane of the
+// wave must call it.
+__device__ __forceinline__ int claim_slots(int32_t* count, int want) {
+    const int lane = (int)threadIdx.x;
+    int incl = want;
+#pragma unroll
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    const int total = __shfl(incl, kBlock - 1);
+    int base = 0;
+    if (lane == 0 && total > 0) base = atomicAdd(count, total);
+    base = __shfl(base, 0);
+    return base + incl - want;
+}
+
+template <typename T, int K, int VEC, int NL, int V>
+__global__ __launch_bounds__(kBlock) void k_render_camera_split(KBatch<1> B, KSplit S) {
+    const int64_t b = xcd_swizzle(blockIdx.x, B.n_blocks);
+    if (b < 0) return;
+    const KJob& J = B.job[0];
+    const KTree& tr = J.tr;
+    const KOpts& op = J.op;
+    const int q = (int)b;
+    const int tile = J.tile_begin + (q >> 2), quad = q & 3;
+    const int tx = tile % J.tiles_x, ty = tile / J.tiles_x;
+    const int lane = threadIdx.x;
+    const int px = tx * 16 + (quad & 1) * 8 + (lane & 7);
+    const int py = ty * 16 + (quad >> 1) * 8 + (lane >> 3);
+    const bool valid = (px < J.cam.W) & (py < J.cam.H);
+    extern __shared__ int po_stack[];
+    int* stk = po_stack + lane;
+    using Smp = FwdSampler<T, K, VEC, NL, false>;
+    Smp smp;
+    Ray r;
+    int want = 0, steps = 0;
+    if (valid) {
+        double ro[3], rd[3];
+        pixel_ray(J.cam, px, py, ro, rd);
+        if (ray_setup(tr, ro, rd, r)) {
+            const double s_first = r.s;
+            fwd_init<T, K, V>(smp, tr, op, r);
+            steps = march<Smp, true>(tr, r, min(S.split_steps, op.max_steps), stk, smp);
+            if (r.more) {
+                if (steps >= op.max_steps)
+                    atomicAdd(&g_po_errors, 1ull);  // the step cap proper
+                else
+                    want = pieces_wanted(r, s_first, steps, S);
+            }
+        }
+    }
+    const int region = (int)(blockIdx.x % kSplitRegions);
+    const int q0 = claim_slots(S.count + region, want);
+    bool handed = false;
+    if (want > 0) {
+        const int rbase = region * kSplitRegionSlots;
+        if (q0 + want <= kSplitRegionSlots) {
+            const int h = rbase + q0;
+            ContHead hd;
+            hd.s = r.s;
+            hd.T = smp.Tl;
+            hd.c0 = smp.c0;
+            hd.c1 = smp.c1;
+            hd.c2 = smp.c2;
+            hd.pix = py * J.cam.W + px;
+            hd.pad = 0;
+            reinterpret_cast<ContHead*>(S.head)[h] = hd;
+            for (int j = 0; j < want; ++j) {
+                S.info[2 * (h + j)] = h;
+                S.info[2 * (h + j) + 1] = j | (want << 8);
+            }
+            handed = true;
+        } else {
+            // region full: mark the slots this ray claimed as unused and finish here
+            for (int qq = q0; qq < min(q0 + want, kSplitRegionSlots); ++qq) S.info[2 * (rbase + qq)] = -1;
+            march<Smp>(tr, r, op.max_steps - steps, stk, smp);
+        }
+    }
+    if (valid && !handed) {
+        const size_t p = (size_t)py * J.cam.W + px;
+        J.rgb[3 * p + 0] = fmaf(smp.Tl, op.bg[0], smp.c0);
+        J.rgb[3 * p + 1] = fmaf(smp.Tl, op.bg[1], smp.c1);
+        J.rgb[3 * p + 2] = fmaf(smp.Tl, op.bg[2], smp.c2);
+    }
+}
+
+__global__ void k_zero_i32(int32_t* __restrict__ p, int n) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = 0;
+}
+
+// Queue slot of this thread, or -1 beyond its region's claimed slots.
+// Workgroup b takes region b % kSplitRegions, so that the workgroups with
+// work come first in dispatch order and each region stays on the XCD whose
+// workgroups filled it (b % 8 is the XCD).
+__device__ __forceinline__ int split_slot(const int32_t* count) {
+#ifdef PO_REGION_MAJOR
+    const int region = (int)(blockIdx.x % kSplitRegions);
+    const int local = (int)(blockIdx.x / kSplitRegions) * kBlock + (int)threadIdx.x;
+#else
+    const int region = (int)(blockIdx.x / (kSplitRegionSlots / kBlock));
+    const int local = (int)(blockIdx.x % (kSplitRegionSlots / kBlock)) * kBlock + (int)threadIdx.x;
+#endif
+    const int n = min(count[region], kSplitRegionSlots);
+    return local < n ? region * kSplitRegionSlots + local : -1;
+}
+
+template <typename T, int K, int VEC, int NL, int V>
+__global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S) {
+    const int q = split_slot(S.count);
+    const int h = q < 0 ? -1 : S.info[2 * q];
+    const KJob& J = B.job[0];
+    using Smp = ChunkSampler<T, K, VEC, NL>;
+    Smp smp;
+    Ray r;
+    int want = 0, steps = 0, pix = 0;
+    extern __shared__ int po_stack[];
+    int* stk = po_stack + threadIdx.x;
+    if (h >= 0) {
+        const int mj = S.info[2 * q + 1];
+        const ContHead hd = reinterpret_cast<const ContHead*>(S.head)[h];
+        pix = hd.pix;
+        if (piece_setup(J, pix, hd.s, 1e300, mj & 255, mj >> 8, r)) {
+            const double s_first = r.s;
+            fwd_init<T, K, V>(smp, J.tr, J.op, r);
+            steps = march<Smp, true>(J.tr, r, min(S.chunk_cap, J.op.max_steps), stk, smp);
+            if (r.more) {
+                if (steps >= J.op.max_steps) {
+                    atomicAdd(&g_po_errors, 1ull);
+                } else {
+                    want = pieces_wanted(r, s_first, steps, S);
+#ifdef PO_MIN_SUB
+                    if (want < PO_MIN_SUB) {
+                        march<Smp>(J.tr, r, J.op.max_steps - steps, stk, smp);
+                        want = 0;
+                    }
+#endif
+                }
+            }
+        }
+    }
+    const int region = (int)(blockIdx.x % kSplitRegions);
+    const int q0 = claim_slots(S.count2 + region, want);
+    int sub = -1;
+    if (want > 0) {
+        const int rbase = region * kSplitRegionSlots;
+        if (q0 + want <= kSplitRegionSlots) {
+            sub = rbase + q0;
+            SubHead sh;
+            sh.lo = r.s;
+            sh.hi = r.s_end;
+            sh.pix = pix;
+            sh.pad[0] = sh.pad[1] = sh.pad[2] = 0;
+            reinterpret_cast<SubHead*>(S.head2)[sub] = sh;
+            for (int j = 0; j < want; ++j) {
+                S.info2[2 * (sub + j)] = sub;
+                S.info2[2 * (sub + j) + 1] = j | (want << 8);
+            }
+        } else {
+            for (int qq = q0; qq < min(q0 + want, kSplitRegionSlots); ++qq) S.info2[2 * (rbase + qq)] = -1;
+            march<Smp>(J.tr, r, J.op.max_steps - steps, stk, smp);
+            want = 0;
+        }
+    }
+    if (h >= 0) {
+        PieceOut o;
+        o.c0 = smp.c0;
+        o.c1 = smp.c1;
+        o.c2 = smp.c2;
+        o.T = smp.Tl;
+        o.Tlast = smp.Tlast;
+        o.sub = sub;
+        o.n_sub = want;
+        o.pad = 0;
+        reinterpret_cast<PieceOut*>(S.part)[q] = o;
+    }
+}
+
+template <typename T, int K, int VEC, int NL, int V>
+__global__ __launch_bounds__(kBlock) void k_render_subchunks(KBatch<1> B, KSplit S) {
+    const int q = split_slot(S.count2);
+    if (q < 0) return;
+    const int h = S.info2[2 * q];
+    if (h < 0) return;
+    const int mj = S.info2[2 * q + 1];
+    const SubHead sh = reinterpret_cast<const SubHead*>(S.head2)[h];
+    const KJob& J = B.job[0];
+    using Smp = ChunkSampler<T, K, VEC, NL>;
+    Smp smp;
+    Ray r;
+    if (piece_setup(J, sh.pix, sh.lo, sh.hi, mj & 255, mj >> 8, r)) {
+        fwd_init<T, K, V>(smp, J.tr, J.op, r);
+        extern __shared__ int po_stack[];
+        march(J.tr, r, J.op.max_steps, po_stack + threadIdx.x, smp);
+    }
+    PieceOut o;
+    o.c0 = smp.c0;
+    o.c1 = smp.c1;
+    o.c2 = smp.c2;
+    o.T = smp.Tl;
+    o.Tlast = smp.Tlast;
+    o.sub = -1;
+    o.n_sub = 0;
+    o.pad = 0;
+    reinterpret_cast<PieceOut*>(S.part2)[q] = o;
+}
+
+// Front-to-back join of one piece with result o into (c, Tp): piece k of n
+// of [a, hi]; a chunk whose remainder was handed on (o.n_sub > 0) ends where
+// its remainder begins.  Returns true when early stopping ends the ray in
+// this piece.
+template <typename T, int K, int VEC, int NL, int V>
+__device__ __forceinline__ bool join_piece(const KJob& J, const KSplit& S, int pix, double a, double hi, int k,
+                                           int n, const PieceOut& o, float& Tp, float (&c)[3]) {
+    if (o.Tlast >= 0.0f && Tp * o.Tlast < J.op.stop_T) {
+        // the walk stops inside this piece: walk it again from Tp
+        double lo, up;
+        piece_bounds(J, pix, a, hi, k, n, lo, up);
+        if (o.n_sub > 0) up = reinterpret_cast<const SubHead*>(S.head2)[o.sub].lo;
+        using Smp = ChunkSampler<T, K, VEC, NL>;
+        Smp smp;
+        smp.Tl = Tp;
+        Ray r;
+        if (piece_setup(J, pix, lo, up, 0, 1, r)) {
+            fwd_init<T, K, V>(smp, J.tr, J.op, r);
+            extern __shared__ int po_stack[];
+            march(J.tr, r, J.op.max_steps, po_stack + threadIdx.x, smp);
+        }
+        c[0] += smp.c0;
+        c[1] += smp.c1;
+        c[2] += smp.c2;
+        Tp = smp.Tl;
+        // (rounding can leave T just above stop_T; then the later pieces still count)
+        return smp.hit;
+    }
+    c[0] = fmaf(Tp, o.c0, c[0]);
+    c[1] = fmaf(Tp, o.c1, c[1]);
+    c[2] = fmaf(Tp, o.c2, c[2]);
+    Tp = Tp * o.T;
+    return false;
+}
+
+template <typename T, int K, int VEC, int NL, int V>
+__global__ __launch_bounds__(kBlock) void k_render_join(KBatch<1> B, KSplit S) {
+    const int q = split_slot(S.count);
+    if (q < 0) return;
+    if (S.info[2 * q] != q) return;  // not the first slot of a ray
+    const int m = S.info[2 * q + 1] >> 8;
+    const ContHead hd = reinterpret_cast<const ContHead*>(S.head)[q];
+    const KJob& J = B.job[0];
+    const PieceOut* part = reinterpret_cast<const PieceOut*>(S.part);
+    const PieceOut* part2 = reinterpret_cast<const PieceOut*>(S.part2);
+    const SubHead* head2 = reinterpret_cast<const SubHead*>(S.head2);
+    float Tp = hd.T;
+    float c[3] = {hd.c0, hd.c1, hd.c2};
+    bool done = false;
+    for (int j = 0; j < m && !done; ++j) {
+        const PieceOut o = part[q + j];
+        done = join_piece<T, K, VEC, NL, V>(J, S, hd.pix, hd.s, 1e300, j, m, o, Tp, c);
+        if (o.n_sub > 0 && !done) {
+            // the remainder's sub-chunks (bounds read only to walk one again)
+            double slo = 0.0, shi = 0.0;
+            for (int k = 0; k < o.n_sub && !done; ++k) {
+                const PieceOut o2 = part2[o.sub + k];
+                if (o2.Tlast >= 0.0f && Tp * o2.Tlast < J.op.stop_T && shi == 0.0) {
+                    const SubHead sh = head2[o.sub];
+                    slo = sh.lo;
+                    shi = sh.hi;
+                }
+                done = join_piece<T, K, VEC, NL, V>(J, S, hd.pix, slo, shi, k, o.n_sub, o2, Tp, c);
+            }
+        }
+    }
+    const size_t p = (size_t)hd.pix;
+    J.rgb[3 * p + 0] = fmaf(Tp, J.op.bg[0], c[0]);
+    J.rgb[3 * p + 1] = fmaf(Tp, J.op.bg[1], c[1]);
+    J.rgb[3 * p + 2] = fmaf(Tp, J.op.bg[2], c[2]);
 }
 
 // Gradient of one ray's samples (App. B.3): the forward colour C is the
@@ -1057,6 +1500,42 @@ hipError_t camera_t(const po_tree* t, int n_jobs, KJob* jobs, int n_blocks, int 
     return hipGetLastError();
 }
 
+template <typename T, int K>
+hipError_t camera_split_t(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
+                          hipStream_t s) {
+    using P = Plan<T, K>;
+    KBatch<1> B;
+    B.job[0] = job;
+    B.n_jobs = 1;
+    B.n_blocks = n_blocks;
+    // counters cleared by a kernel rather than a memset node, so that the
+    // launches can also be captured in a graph
+    hipLaunchKernelGGL(k_zero_i32, dim3(2), dim3(kSplitRegions), 0, s, S.count, 2 * kSplitRegions);
+    dim3 g1((unsigned)grid_for(n_blocks)), g2((unsigned)(kSplitSlots / kBlock)), blk(kBlock);
+    const size_t lds = stack_bytes(job.tr.depth);
+    const bool fast = use_fast<T, K>(t);
+#define PO_SPLIT(VEC_, NL_, V_)                                                                        \
+    do {                                                                                              \
+        hipLaunchKernelGGL((k_render_camera_split<T, K, VEC_, NL_, V_>), g1, blk, lds, s, B, S);     \
+        hipLaunchKernelGGL((k_render_chunks<T, K, VEC_, NL_, V_>), g2, blk, lds, s, B, S);           \
+        hipLaunchKernelGGL((k_render_subchunks<T, K, VEC_, NL_, V_>), g2, blk, lds, s, B, S);        \
+        hipLaunchKernelGGL((k_render_join<T, K, VEC_, NL_, V_>), g2, blk, lds, s, B, S);             \
+    } while (0)
+    if (variant == PO_FWD_SG) {
+        if (fast)
+            PO_SPLIT(P::FAST_VEC, P::FAST_NL, PO_FWD_SG);
+        else
+            PO_SPLIT(4, P::GEN_NL, PO_FWD_SG);
+    } else {
+        if (fast)
+            PO_SPLIT(P::FAST_VEC, P::FAST_NL, PO_FWD_SH);
+        else
+            PO_SPLIT(4, P::GEN_NL, PO_FWD_SH);
+    }
+#undef PO_SPLIT
+    return hipGetLastError();
+}
+
 template <int K>
 hipError_t backward_t(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
                       const float* rgb_fwd, const float* grad, float* gsig, float* gsh, hipStream_t s) {
@@ -1106,6 +1585,15 @@ hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, i
         PO_DISPATCH_K(first->K, (camera_t<float, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, variant, s)));
     } else {
         PO_DISPATCH_K(first->K, (camera_t<__half, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, variant, s)));
+    }
+}
+
+hipError_t po_launch_camera_split(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
+                                  hipStream_t s) {
+    if (t->desc.dtype == PO_F32) {
+        PO_DISPATCH_K(t->K, (camera_split_t<float, KK>(t, job, n_blocks, variant, S, s)));
+    } else {
+        PO_DISPATCH_K(t->K, (camera_split_t<__half, KK>(t, job, n_blocks, variant, S, s)));
     }
 }
 

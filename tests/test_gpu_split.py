@@ -1,0 +1,197 @@
+"""The split camera render against the one-pass render and the FP64 oracle.
+
+Camera renders of 2^16 pixels or more walk every ray for a bounded number of
+cells, hand the rays with cells left on as chunks walked in parallel, and join
+the chunk results front to back (Sec. 3, eqn:quad: the composite of a range
+of segments acts on what lies behind it through its colour and
+transmittance).  Where early stopping ends a ray inside a chunk, the join
+walks that chunk again from the known transmittance.
+
+The scene is a ball of fog: finest cells of moderate density, so that rays
+through its middle walk a hundred cells or more and reach T < 1e-4 deep inside
+(the chunk walked again), while rays near its rim leave it first.  The
+one-pass render of the same pixels comes from render_batch, which does not
+split.  The two differ by float rounding only; where T lands within rounding
+of stop_T the two may stop one cell apart, which moves at most T = stop_T of
+weight.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_14024_amd import scenes
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def po():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2103_14024_amd as po
+
+    po.reset_device_errors()
+    return po
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", file=sys.stderr, flush=True)
+
+
+def fog_scene(depth=7, radius=0.8, sh_degree=1, seed=31):
+    """Every finest cell whose centre lies in a ball, sigma ~ U(4, 10)."""
+    n = 1 << depth
+    c = (np.arange(n) + 0.5) * (2.0 / n) - 1.0
+    x, y, z = np.meshgrid(c, c, c, indexing="ij")
+    ijk = np.argwhere(x * x + y * y + z * z <= radius * radius).astype(np.int32)
+    cells = np.column_stack([np.full(len(ijk), depth, np.int32), ijk])
+    rng = np.random.default_rng(seed)
+    K = (sh_degree + 1) ** 2
+    sigma = rng.uniform(4.0, 10.0, len(cells)).astype(np.float32)
+    sh = rng.normal(0.0, 0.5, (len(cells), 3, K)).astype(np.float32)
+    return dict(depth=depth, sh_degree=sh_degree, center=(0.0, 0.0, 0.0), half=1.0, cells=cells, sigma=sigma, sh=sh)
+
+
+@pytest.fixture(scope="module")
+def fog(po):
+    s = fog_scene()
+    _say(f"fog ball: {len(s['cells'])} leaves")
+    tree = po.Tree.from_scene(s)
+    ot = oracle.OracleTree(s["depth"], s["sh_degree"], s["center"], s["half"], s["cells"], s["sigma"], s["sh"])
+    return s, tree, ot
+
+
+def _cam(po, W, H, seed=3, radius=2.6, fov=40.0):
+    pose = scenes.hemisphere_poses(1, radius, seed)[0]
+    return po.Camera(pose, W, H, *scenes.intrinsics(W, H, fov)), pose
+
+
+def _one_pass(po, tree, cam, stop_T, aux=False):
+    import torch
+
+    out = torch.empty((cam.height, cam.width, 3), device="cuda")
+    a = torch.empty((cam.height, cam.width, 4), device="cuda") if aux else None
+    po.render_batch([po.Job(tree, cam, out, stop_T=stop_T, aux_out=a)])
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), (a.cpu().numpy() if aux else None)
+
+
+def _oracle_pixels(ot, cam, pose, idx, stop_T):
+    f32 = [float(np.float32(v)) for v in (cam.fx, cam.fy, cam.cx, cam.cy)]
+    o, d = oracle.camera_rays(np.asarray(pose, np.float32).astype(np.float64), cam.width, cam.height, *f32)
+    ref, T, ns, _ = ot.render_rays(o[idx], d[idx], gamma=stop_T)
+    return ref, T
+
+
+@pytest.mark.parametrize("stop_T", [0.0, 1e-4])
+def test_split_matches_oracle_and_one_pass(po, fog, stop_T):
+    s, tree, ot = fog
+    W = H = 256
+    cam, pose = _cam(po, W, H)
+    _say(f"split render {W}x{H}, stop_T {stop_T}")
+    img = po.render_camera(tree, cam, stop_T=stop_T).cpu().numpy()
+    one, aux = _one_pass(po, tree, cam, stop_T, aux=True)
+    steps, T = aux[..., 2].reshape(-1), aux[..., 0].reshape(-1)
+    long_rays = steps > 32
+    stopped_late = long_rays & (T < stop_T)
+    _say(f"rays past 32 cells: {long_rays.sum()}, of which stopped: {stopped_late.sum()}; max steps {steps.max():.0f}")
+    assert long_rays.sum() > 15000
+    if stop_T > 0:
+        # early stopping inside the handed-on part of many rays
+        assert stopped_late.sum() > 5000
+    d = np.abs(img - one).max(-1).reshape(-1)
+    _say(f"split vs one pass: max {d.max():.2e}, pixels above 1e-5: {(d > 1e-5).sum()}")
+    assert np.mean(d > 1e-5) <= 1e-4 and d.max() <= stop_T + 1e-5
+    # oracle: random pixels and the longest walks
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([rng.choice(W * H, 2000, replace=False), np.argsort(-steps)[:300]]))
+    ref, Tref = _oracle_pixels(ot, cam, pose, idx, stop_T)
+    err = np.abs(img.reshape(-1, 3)[idx] - ref).max(1)
+    _say(f"split vs oracle on {len(idx)} pixels: max {err.max():.2e} mean {err.mean():.2e}")
+    assert err.max() <= TOL
+    if stop_T > 0:
+        assert np.sum(Tref < stop_T) > 300
+    assert po.device_errors() == 0
+
+
+def test_split_early_stop_near_one_percent(po, fog):
+    # stop_T = 1e-2 (the paper's threshold): stops come early in most walks
+    s, tree, ot = fog
+    cam, pose = _cam(po, 320, 240, seed=5)
+    img = po.render_camera(tree, cam, stop_T=1e-2).cpu().numpy()
+    one, _ = _one_pass(po, tree, cam, 1e-2)
+    d = np.abs(img - one).max(-1)
+    _say(f"stop_T 1e-2: split vs one pass max {d.max():.2e}, pixels above 1e-5: {(d > 1e-5).sum()}")
+    assert np.mean(d > 1e-5) <= 1e-3 and d.max() <= 1e-2 + 1e-5
+    assert po.device_errors() == 0
+
+
+@pytest.mark.parametrize("kind", ["f16", "sg"])
+def test_split_forms(po, fog, kind):
+    s, _, _ = fog
+    if kind == "sg":
+        s = dict(s, lobes=scenes.sg_lobes(4, 41))
+        tree = po.Tree.from_scene(s)
+    else:
+        tree = po.Tree.from_scene(s, dtype="f16")
+    cam, pose = _cam(po, 300, 240, seed=9)
+    _say(f"split render, {kind} tree")
+    img = po.render_camera(tree, cam, stop_T=1e-4).cpu().numpy()
+    one, _ = _one_pass(po, tree, cam, 1e-4)
+    d = np.abs(img - one).max(-1)
+    _say(f"{kind}: split vs one pass max {d.max():.2e}")
+    assert np.mean(d > 1e-5) <= 1e-4 and d.max() <= 1e-4 + 1e-5
+    sig, sh = tree.leaf_values()
+    ot = oracle.OracleTree(s["depth"], s["sh_degree"], s["center"], s["half"], s["cells"], sig, sh,
+                           lobes=s.get("lobes"))
+    rng = np.random.default_rng(11)
+    idx = rng.choice(300 * 240, 1500, replace=False)
+    ref, _ = _oracle_pixels(ot, cam, pose, idx, 1e-4)
+    err = np.abs(img.reshape(-1, 3)[idx] - ref).max(1)
+    _say(f"{kind}: split vs oracle max {err.max():.2e}")
+    assert err.max() <= TOL
+    assert po.device_errors() == 0
+
+
+def test_split_queue_overflow(po, fog):
+    # 2048 x 2048 rays, most of them long: far more chunks than the queue
+    # holds, so many rays finish their walk in the first kernel
+    s, tree, ot = fog
+    W = H = 2048
+    cam, pose = _cam(po, W, H, seed=13, radius=2.2)
+    _say(f"split render {W}x{H} (queue overflow)")
+    img = po.render_camera(tree, cam, stop_T=1e-4).cpu().numpy()
+    one, _ = _one_pass(po, tree, cam, 1e-4)
+    d = np.abs(img - one).max(-1).reshape(-1)
+    _say(f"overflow: split vs one pass max {d.max():.2e}, pixels above 1e-5: {(d > 1e-5).sum()}")
+    assert np.mean(d > 1e-5) <= 1e-4 and d.max() <= 1e-4 + 1e-5
+    rng = np.random.default_rng(19)
+    idx = rng.choice(W * H, 2000, replace=False)
+    ref, _ = _oracle_pixels(ot, cam, pose, idx, 1e-4)
+    err = np.abs(img.reshape(-1, 3)[idx] - ref).max(1)
+    _say(f"overflow: split vs oracle max {err.max():.2e}")
+    assert err.max() <= TOL
+    assert po.device_errors() == 0
+
+
+def test_split_repeated_and_small(po, fog):
+    # repeated frames reuse the queue; a small image below the split size in
+    # between renders in one pass, identical to the batch path
+    import torch
+
+    s, tree, ot = fog
+    cam, _ = _cam(po, 256, 256, seed=3)
+    a = po.render_camera(tree, cam, stop_T=1e-4)
+    small, _ = _cam(po, 64, 48, seed=3)
+    sm = po.render_camera(tree, small, stop_T=1e-4).cpu().numpy()
+    one, _ = _one_pass(po, tree, small, 1e-4)
+    assert np.array_equal(sm, one)
+    for _ in range(3):
+        b = po.render_camera(tree, cam, stop_T=1e-4)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+    assert po.device_errors() == 0
