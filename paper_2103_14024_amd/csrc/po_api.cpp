@@ -74,13 +74,13 @@ bool split_queue(void* stream, KSplit* S) {
     S->count = reinterpret_cast<int32_t*>(p);
     S->count2 = S->count + kSplitRegions;
     p += 512;
-    S->info = reinterpret_cast<int32_t*>(p);
-    S->head = p + n * 8;
-    S->part = p + n * 40;
-    p += n * 72;
-    S->info2 = reinterpret_cast<int32_t*>(p);
-    S->head2 = p + n * 8;
-    S->part2 = p + n * 40;
+    S->info = reinterpret_cast<int4*>(p);
+    S->head = p + n * 16;
+    S->part = p + n * 48;
+    p += n * 80;
+    S->info2 = reinterpret_cast<int4*>(p);
+    S->head2 = p + n * 16;
+    S->part2 = p + n * 48;
     S->split_steps = PO_SPLIT_STEPS;
     S->chunk_steps = PO_CHUNK_STEPS;
     S->chunk_cap = PO_CHUNK_CAP;

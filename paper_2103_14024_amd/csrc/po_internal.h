@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime_api.h>
+#include <hip/hip_vector_types.h>
 #include <stdint.h>
 
 #include "plenoctree.h"
@@ -98,10 +99,10 @@ constexpr int kSplitMaxChunks = 16;
 struct KSplit {
     int32_t* count;        // [kSplitRegions] chunk slots claimed (may exceed the region); count2 follows
     int32_t* count2;       // [kSplitRegions] sub-chunk slots claimed
-    int32_t* info;         // [kSplitSlots][2] first slot of the ray (-1: unused), chunk | chunk count << 8
+    int4* info;            // [kSplitSlots] {first chunk slot of the ray (-1: unused), chunk | count << 8, next chunk slot, 0}
     void* head;            // [kSplitSlots] 32-byte ray states, at the first slot of each ray
     void* part;            // [kSplitSlots] 32-byte chunk results
-    int32_t* info2;        // [kSplitSlots][2] first slot of the remainder (-1: unused), piece | count << 8
+    int4* info2;           // [kSplitSlots] the same for the sub-chunks of remainders
     void* head2;           // [kSplitSlots] 32-byte remainders, at their first slot
     void* part2;           // [kSplitSlots] 32-byte sub-chunk results
     int32_t split_steps;   // cells walked before a ray is handed on
@@ -110,7 +111,7 @@ struct KSplit {
     float ub_frac;         // pieces cover at least this fraction of the finest-cell faces ahead
 };
 // Device bytes of the queues (counters, then info, head, part of each).
-constexpr size_t kSplitBytes = 512 + 2 * (size_t)kSplitSlots * (8 + 32 + 32);
+constexpr size_t kSplitBytes = 512 + 2 * (size_t)kSplitSlots * (16 + 32 + 32);
 
 struct po_tree {
     po_tree_desc desc;

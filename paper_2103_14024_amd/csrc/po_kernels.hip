@@ -870,22 +870,44 @@ __device__ __forceinline__ int pieces_wanted(const Ray& r, double s_first, int s
     return (int)fmin(fmax(ceil(est / (double)S.chunk_steps), 1.0), (double)kSplitMaxChunks);
 }
 
-// One slot claim per wave: returns this lane's first slot in its region
-// (want > 0) from an inclusive prefix sum over the wave.  Every lane of the
-// wave must call it.
-__device__ __forceinline__ int claim_slots(int32_t* count, int want) {
+// Claims the wave's pieces in one atomic: sum(want) slots of a region, laid
+// out level-major (piece 0 of every lane that wants pieces, in lane order,
+// then piece 1, ...), so that a wave of consecutive slots walks neighbouring
+// rays at similar depths.  Writes every claimed slot's info {first slot of
+// its piece list, piece | count << 8, next slot or -1, 0} and returns this
+// lane's first slot, or -1 (want == 0, or the region cannot hold the claim:
+// its claimed slots are then marked unused).  Every lane of the wave must
+// call it.
+__device__ __forceinline__ int claim_pieces(int32_t* count, int4* __restrict__ info, int region, int want) {
     const int lane = (int)threadIdx.x;
-    int incl = want;
+    int tot = want;
 #pragma unroll
-    for (int o = 1; o < kBlock; o <<= 1) {
-        const int v = __shfl_up(incl, o);
-        if (lane >= o) incl += v;
-    }
-    const int total = __shfl(incl, kBlock - 1);
+    for (int o = kBlock / 2; o >= 1; o >>= 1) tot += __shfl_xor(tot, o);
+    if (tot == 0) return -1;
     int base = 0;
-    if (lane == 0 && total > 0) base = atomicAdd(count, total);
+    if (lane == 0) base = atomicAdd(count + region, tot);
     base = __shfl(base, 0);
-    return base + incl - want;
+    const int rbase = region * kSplitRegionSlots;
+    if (base + tot > kSplitRegionSlots) {
+        for (int i = base + lane; i < min(base + tot, kSplitRegionSlots); i += kBlock) info[rbase + i].x = -1;
+        return -1;
+    }
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t mk = __ballot(want > 0);
+    int at = rbase + base, first = -1;
+    for (int j = 0; j < kSplitMaxChunks && mk != 0ull; ++j) {
+        const uint64_t mk1 = __ballot(want > j + 1);
+        const int at1 = at + __popcll(mk);
+        if (want > j) {
+            const int slot = at + __popcll(mk & below);
+            if (j == 0) first = slot;
+            const int next = want > j + 1 ? at1 + __popcll(mk1 & below) : -1;
+            info[slot] = make_int4(first, j | (want << 8), next, 0);
+        }
+        at = at1;
+        mk = mk1;
+    }
+    return first;
 }
 
 template <typename T, int K, int VEC, int NL, int V>
@@ -923,13 +945,10 @@ __global__ __launch_bounds__(kBlock) void k_render_camera_split(KBatch<1> B, KSp
             }
         }
     }
-    const int region = (int)(blockIdx.x % kSplitRegions);
-    const int q0 = claim_slots(S.count + region, want);
+    const int h = claim_pieces(S.count, S.info, (int)(blockIdx.x % kSplitRegions), want);
     bool handed = false;
     if (want > 0) {
-        const int rbase = region * kSplitRegionSlots;
-        if (q0 + want <= kSplitRegionSlots) {
-            const int h = rbase + q0;
+        if (h >= 0) {
             ContHead hd;
             hd.s = r.s;
             hd.T = smp.Tl;
@@ -939,15 +958,9 @@ __global__ __launch_bounds__(kBlock) void k_render_camera_split(KBatch<1> B, KSp
             hd.pix = py * J.cam.W + px;
             hd.pad = 0;
             reinterpret_cast<ContHead*>(S.head)[h] = hd;
-            for (int j = 0; j < want; ++j) {
-                S.info[2 * (h + j)] = h;
-                S.info[2 * (h + j) + 1] = j | (want << 8);
-            }
             handed = true;
         } else {
-            // region full: mark the slots this ray claimed as unused and finish here
-            for (int qq = q0; qq < min(q0 + want, kSplitRegionSlots); ++qq) S.info[2 * (rbase + qq)] = -1;
-            march<Smp>(tr, r, op.max_steps - steps, stk, smp);
+            march<Smp>(tr, r, op.max_steps - steps, stk, smp);  // region full: finish here
         }
     }
     if (valid && !handed) {
@@ -982,7 +995,8 @@ __device__ __forceinline__ int split_slot(const int32_t* count) {
 template <typename T, int K, int VEC, int NL, int V>
 __global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S) {
     const int q = split_slot(S.count);
-    const int h = q < 0 ? -1 : S.info[2 * q];
+    const int4 in = q < 0 ? make_int4(-1, 0, -1, 0) : S.info[q];
+    const int h = in.x;
     const KJob& J = B.job[0];
     using Smp = ChunkSampler<T, K, VEC, NL>;
     Smp smp;
@@ -991,7 +1005,7 @@ __global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S)
     extern __shared__ int po_stack[];
     int* stk = po_stack + threadIdx.x;
     if (h >= 0) {
-        const int mj = S.info[2 * q + 1];
+        const int mj = in.y;
         const ContHead hd = reinterpret_cast<const ContHead*>(S.head)[h];
         pix = hd.pix;
         if (piece_setup(J, pix, hd.s, 1e300, mj & 255, mj >> 8, r)) {
@@ -1013,26 +1027,17 @@ __global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S)
             }
         }
     }
-    const int region = (int)(blockIdx.x % kSplitRegions);
-    const int q0 = claim_slots(S.count2 + region, want);
-    int sub = -1;
+    int sub = claim_pieces(S.count2, S.info2, (int)(blockIdx.x % kSplitRegions), want);
     if (want > 0) {
-        const int rbase = region * kSplitRegionSlots;
-        if (q0 + want <= kSplitRegionSlots) {
-            sub = rbase + q0;
+        if (sub >= 0) {
             SubHead sh;
             sh.lo = r.s;
             sh.hi = r.s_end;
             sh.pix = pix;
             sh.pad[0] = sh.pad[1] = sh.pad[2] = 0;
             reinterpret_cast<SubHead*>(S.head2)[sub] = sh;
-            for (int j = 0; j < want; ++j) {
-                S.info2[2 * (sub + j)] = sub;
-                S.info2[2 * (sub + j) + 1] = j | (want << 8);
-            }
         } else {
-            for (int qq = q0; qq < min(q0 + want, kSplitRegionSlots); ++qq) S.info2[2 * (rbase + qq)] = -1;
-            march<Smp>(J.tr, r, J.op.max_steps - steps, stk, smp);
+            march<Smp>(J.tr, r, J.op.max_steps - steps, stk, smp);  // region full: finish here
             want = 0;
         }
     }
@@ -1054,9 +1059,10 @@ template <typename T, int K, int VEC, int NL, int V>
 __global__ __launch_bounds__(kBlock) void k_render_subchunks(KBatch<1> B, KSplit S) {
     const int q = split_slot(S.count2);
     if (q < 0) return;
-    const int h = S.info2[2 * q];
+    const int4 in = S.info2[q];
+    const int h = in.x;
     if (h < 0) return;
-    const int mj = S.info2[2 * q + 1];
+    const int mj = in.y;
     const SubHead sh = reinterpret_cast<const SubHead*>(S.head2)[h];
     const KJob& J = B.job[0];
     using Smp = ChunkSampler<T, K, VEC, NL>;
@@ -1118,8 +1124,9 @@ template <typename T, int K, int VEC, int NL, int V>
 __global__ __launch_bounds__(kBlock) void k_render_join(KBatch<1> B, KSplit S) {
     const int q = split_slot(S.count);
     if (q < 0) return;
-    if (S.info[2 * q] != q) return;  // not the first slot of a ray
-    const int m = S.info[2 * q + 1] >> 8;
+    const int4 in = S.info[q];
+    if (in.x != q) return;  // not the first slot of a ray
+    const int m = in.y >> 8;
     const ContHead hd = reinterpret_cast<const ContHead*>(S.head)[q];
     const KJob& J = B.job[0];
     const PieceOut* part = reinterpret_cast<const PieceOut*>(S.part);
@@ -1128,14 +1135,18 @@ __global__ __launch_bounds__(kBlock) void k_render_join(KBatch<1> B, KSplit S) {
     float Tp = hd.T;
     float c[3] = {hd.c0, hd.c1, hd.c2};
     bool done = false;
+    int qj = q;
     for (int j = 0; j < m && !done; ++j) {
-        const PieceOut o = part[q + j];
+        const PieceOut o = part[qj];
+        qj = S.info[qj].z;
         done = join_piece<T, K, VEC, NL, V>(J, S, hd.pix, hd.s, 1e300, j, m, o, Tp, c);
         if (o.n_sub > 0 && !done) {
             // the remainder's sub-chunks (bounds read only to walk one again)
             double slo = 0.0, shi = 0.0;
+            int qk = o.sub;
             for (int k = 0; k < o.n_sub && !done; ++k) {
-                const PieceOut o2 = part2[o.sub + k];
+                const PieceOut o2 = part2[qk];
+                qk = S.info2[qk].z;
                 if (o2.Tlast >= 0.0f && Tp * o2.Tlast < J.op.stop_T && shi == 0.0) {
                     const SubHead sh = head2[o.sub];
                     slo = sh.lo;
