@@ -195,3 +195,68 @@ def test_split_repeated_and_small(po, fog):
         torch.cuda.synchronize()
         assert torch.equal(a, b)
     assert po.device_errors() == 0
+
+
+@pytest.mark.parametrize("deg,sg,dtype", [(0, False, "f32"), (1, False, "f16"), (2, False, "f32"), (4, False, "f32"),
+                                          (4, True, "f16")])
+def test_split_every_basis(po, deg, sg, dtype):
+    # every compiled K (1, 4, 9, 25) and SG-25 through the split render, on
+    # the depth-7 blob band at 320 x 256 pixels
+    s = scenes.scene_blobs(depth=7, sh_degree=deg, seed=6, data_seed=7)
+    K = (deg + 1) ** 2
+    if sg:
+        s = dict(s, lobes=scenes.sg_lobes(K, 43))
+    tree = po.Tree.from_scene(s, dtype=dtype)
+    cam, pose = _cam(po, 320, 256, seed=21, radius=3.0)
+    _say(f"split render K={K} sg={sg} {dtype}")
+    img = po.render_camera(tree, cam, stop_T=1e-4).cpu().numpy()
+    one, aux = _one_pass(po, tree, cam, 1e-4, aux=True)
+    assert (aux[..., 2] > 32).sum() > 500  # walks long enough to be split
+    d = np.abs(img - one).max(-1)
+    assert np.mean(d > 1e-5) <= 1e-4 and d.max() <= 1e-4 + 1e-5
+    sig, sh = tree.leaf_values()
+    ot = oracle.OracleTree(s["depth"], deg, s["center"], s["half"], s["cells"], sig, sh, lobes=s.get("lobes"))
+    rng = np.random.default_rng(23)
+    idx = np.unique(np.concatenate([rng.choice(320 * 256, 1200, replace=False),
+                                    np.argsort(-aux[..., 2].reshape(-1))[:200]]))
+    ref, _ = _oracle_pixels(ot, cam, pose, idx, 1e-4)
+    err = np.abs(img.reshape(-1, 3)[idx] - ref).max(1)
+    _say(f"K={K} sg={sg} {dtype}: split vs oracle max {err.max():.2e}")
+    assert err.max() <= TOL
+    assert po.device_errors() == 0
+
+
+def test_split_max_depth(po):
+    # the deepest tree the ABI accepts (depth 15): a dense cluster of finest
+    # cells plus coarse leaves, seen by a 256 x 256 camera close to the cluster
+    from paper_2103_14024_amd import _lib as L
+
+    depth = L.PO_MAX_DEPTH
+    base = (1 << depth) // 2 - 12
+    g = np.stack(np.meshgrid(*[np.arange(24)] * 3, indexing="ij"), -1).reshape(-1, 3) + base
+    fine = np.column_stack([np.full(len(g), depth), g])
+    coarse = np.array([[3, 0, 0, 0], [3, 7, 7, 7], [2, 0, 3, 1], [4, 15, 2, 9]])
+    cells = np.concatenate([fine, coarse]).astype(np.int32)
+    sigma, sh = scenes.leaf_values(len(cells), 1, 16, mu=7.0, s=0.3)
+    s = dict(depth=depth, sh_degree=1, center=(0.0, 0.0, 0.0), half=1.0, cells=cells, sigma=sigma, sh=sh)
+    tree = po.Tree.from_scene(s)
+    cell = 2.0 / (1 << depth)
+    pose = scenes.look_at(np.array([0.3, -0.2, 0.25]) * 24 * cell * 3, (0.0, 0.0, 0.0))
+    fx, fy, cx, cy = scenes.intrinsics(256, 256, 60.0)
+    cam = po.Camera(pose, 256, 256, fx, fy, cx, cy)
+    _say("split render, depth-15 tree")
+    img = po.render_camera(tree, cam, stop_T=1e-4).cpu().numpy()
+    one, aux = _one_pass(po, tree, cam, 1e-4, aux=True)
+    _say(f"depth 15: max steps {aux[..., 2].max():.0f}, rays past 32 cells {(aux[..., 2] > 32).sum()}")
+    assert (aux[..., 2] > 32).sum() > 2000
+    d = np.abs(img - one).max(-1)
+    assert np.mean(d > 1e-5) <= 1e-4 and d.max() <= 1e-4 + 1e-5
+    ot = oracle.OracleTree(depth, 1, s["center"], s["half"], cells, sigma, sh)
+    rng = np.random.default_rng(29)
+    idx = np.unique(np.concatenate([rng.choice(256 * 256, 1500, replace=False),
+                                    np.argsort(-aux[..., 2].reshape(-1))[:200]]))
+    ref, _ = _oracle_pixels(ot, cam, pose, idx, 1e-4)
+    err = np.abs(img.reshape(-1, 3)[idx] - ref).max(1)
+    _say(f"depth 15: split vs oracle max {err.max():.2e}")
+    assert err.max() <= TOL
+    assert po.device_errors() == 0
