@@ -201,6 +201,8 @@ po_status po_tree_destroy(po_tree* t);
  * d_aux[n][4].  The colour is sum_i T_i (1 - exp(-sigma_i delta_i)) c_i +
  * T_N bg over the data segments met before the early stop (Sec. 3 eqn:quad,
  * App. B.3), c_i = sigmoid(sum_k sh[leaf][ch][k] Y_k(d)) (Sec. 4.1).
+ * Lists of at least 2^18 rays without viewer options are rendered in pieces
+ * as po_render_camera describes (same queue, same equality up to rounding).
  * Errors: PO_ERR_INVALID (NULL tree/opts/arrays with n > 0, n < 0, bad
  * options), PO_ERR_DEVICE (launch failure). */
 po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, const float* d_dirs,

@@ -109,6 +109,9 @@ struct KSplit {
     int32_t chunk_steps;   // target cells per chunk
     int32_t chunk_cap;     // cells a chunk walks before its remainder is handed on
     float ub_frac;         // pieces cover at least this fraction of the finest-cell faces ahead
+    const float* ray_o;    // ray-list renders: origins [n_rays][3] (camera renders: unused)
+    const float* ray_d;    // ray-list renders: directions [n_rays][3]
+    int64_t n_rays;
 };
 // Device bytes of the queues (counters, then info, head, part of each).
 constexpr size_t kSplitBytes = 512 + 2 * (size_t)kSplitSlots * (16 + 32 + 32);
@@ -140,11 +143,15 @@ hipError_t po_launch_backward(const po_tree* t, int64_t n, const float* o, const
 // workgroups, four per 16x16 tile.
 hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, int variant,
                                  hipStream_t s);
-// One camera job as the split render (plain SH or SG variants of float32 or
-// float16 trees): clears the queue counters and launches the three kernels.
+// One camera job as the split render (plain SH, SG or codebook variants):
+// clears the queue counters and launches the four render kernels.
 // The queue must not be in use by work on another stream.
 hipError_t po_launch_camera_split(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
                                   hipStream_t s);
+// n rays (n < 2^31) of a plain SH, SG or codebook tree as the split render;
+// the queue must not be in use by work on another stream.
+hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
+                                float* rgb, const KSplit& S, hipStream_t s);
 hipError_t po_launch_camera_rays(const KCam& cam, float* o, float* d, hipStream_t s);
 // Visibility filter: mode 0 alpha, 1 contribution; weight[n_leaves] raised in place, alpha[H*W] or nullptr.
 hipError_t po_launch_leaf_weights(const po_tree* t, const KCam& cam, const KOpts& op, int mode, float* weight,

@@ -23,6 +23,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <type_traits>
 
 #include "po_internal.h"
@@ -516,38 +517,6 @@ struct FwdSampler {
     }
 };
 
-// One chunk [s_lo, s_hi] of a split ray.  The chunk composites from T = 1
-// (or from a known transmittance when it is walked again); because
-// compositing is associative, chunk results combine front to back with the
-// over operator.  Early stopping is tested where the sequential walk tests it,
-// at the end of a cell: a sample whose cell continues past s_hi (cut by the
-// chunk boundary) is composited without a test, and its remainder, the first
-// sample of the next chunk, carries the test.  Tlast is T after the last
-// tested sample (-1: none); the chunk stops itself once T < stopT there,
-// since its walk cannot matter past that point for any transmittance in
-// front of it.
-template <typename T, int K, int VEC, int NL>
-struct ChunkSampler : FwdSampler<T, K, VEC, NL, false> {
-    using Base = FwdSampler<T, K, VEC, NL, false>;
-    static constexpr bool kClip = true;
-    static constexpr bool kChunk = true;
-    bool cpl_next = true, cpl = true;
-    bool hit = false;  // stopped by stopT
-    float Tlast = -1.0f;
-
-    __device__ __forceinline__ void issue(int leaf, float d, float t_in) {
-        Base::issue(leaf, d, t_in);
-        cpl = cpl_next;
-    }
-    __device__ __forceinline__ bool consume() {
-        const bool st = Base::consume();
-        if (!cpl) return false;
-        Tlast = this->Tl;
-        hit |= st;
-        return st;
-    }
-};
-
 // Codebook leaves (App. B.2): the record holds one 16-bit codebook position
 // per basis function; consume() gathers the K float16 colours (8 bytes each,
 // from the per-basis codebooks) and shades as an SH leaf.  The gathers are in
@@ -602,6 +571,43 @@ struct CbSampler {
         return Tl < stopT;
     }
 };
+
+// One chunk [s_lo, s_hi] of a split ray.  The chunk composites from T = 1
+// (or from a known transmittance when it is walked again); because
+// compositing is associative, chunk results combine front to back with the
+// over operator.  Early stopping is tested where the sequential walk tests it,
+// at the end of a cell: a sample whose cell continues past s_hi (cut by the
+// chunk boundary) is composited without a test, and its remainder, the first
+// sample of the next chunk, carries the test.  Tlast is T after the last
+// tested sample (-1: none); the chunk stops itself once T < stopT there,
+// since its walk cannot matter past that point for any transmittance in
+// front of it.
+template <class Base>
+struct ChunkOf : Base {
+    static constexpr bool kClip = true;
+    static constexpr bool kChunk = true;
+    bool cpl_next = true, cpl = true;
+    bool hit = false;  // stopped by stopT
+    float Tlast = -1.0f;
+
+    __device__ __forceinline__ void issue(int leaf, float d, float t_in) {
+        Base::issue(leaf, d, t_in);
+        cpl = cpl_next;
+    }
+    __device__ __forceinline__ bool consume() {
+        const bool st = Base::consume();
+        if (!cpl) return false;
+        Tlast = this->Tl;
+        hit |= st;
+        return st;
+    }
+};
+
+// Samplers of the split render: the first walk's, and a piece's.
+template <typename T, int K, int VEC, int NL, int V>
+using FirstSampler = std::conditional_t<V == PO_FWD_CB, CbSampler<K, VEC, NL>, FwdSampler<T, K, VEC, NL, false>>;
+template <typename T, int K, int VEC, int NL, int V>
+using ChunkSampler = ChunkOf<FirstSampler<T, K, VEC, NL, V>>;
 
 // Renders one ray: colour (background included), final T, samples, steps
 // and, in the viewer variant, the expected termination distance, SH subsets
@@ -830,18 +836,39 @@ __device__ __forceinline__ void fwd_init(Smp& smp, const KTree& tr, const KOpts&
     smp.sh_end = tr.sh_bytes;
     smp.rec_bytes = (uint32_t)tr.stride * (uint32_t)sizeof(T);
     smp.stopT = op.stop_T;
+    if constexpr (V == PO_FWD_CB) {
+        smp.cb_basis_bytes = (uint32_t)tr.cb_entries * 8u;
+        smp.cb = raw_rsrc(tr.codebook, (uint32_t)K * smp.cb_basis_bytes);
+    }
     if constexpr (V == PO_FWD_SG)
         sg_basis<K>(tr.lobes, r.dn[0], r.dn[1], r.dn[2], smp.Y);
     else
         sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], smp.Y);
 }
 
-// Piece k of n of the parameter range [a, hi] of a pixel's ray: equal
-// intervals of [a, min(hi, box exit)], the last one running to hi itself.
-// Sets up r for the walk of the piece; false when the piece is empty.
-__device__ __forceinline__ bool piece_setup(const KJob& J, int pix, double a, double hi, int k, int n, Ray& r) {
+// Ray idx of a split render: pixel idx = py * W + px of the job's camera
+// (SRC 0) or entry idx of the caller's ray arrays (SRC 1).
+template <int SRC>
+__device__ __forceinline__ void ray_of(const KJob& J, const KSplit& S, int idx, double (&ro)[3], double (&rd)[3]) {
+    if constexpr (SRC == 0) {
+        pixel_ray(J.cam, idx % J.cam.W, idx / J.cam.W, ro, rd);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ro[k] = (double)S.ray_o[3 * (size_t)idx + k];
+            rd[k] = (double)S.ray_d[3 * (size_t)idx + k];
+        }
+    }
+}
+
+// Piece k of n of the parameter range [a, hi] of ray idx: equal intervals of
+// [a, min(hi, box exit)], the last one running to hi itself.  Sets up r for
+// the walk of the piece; false when the piece is empty.
+template <int SRC>
+__device__ __forceinline__ bool piece_setup(const KJob& J, const KSplit& S, int idx, double a, double hi, int k,
+                                            int n, Ray& r) {
     double ro[3], rd[3];
-    pixel_ray(J.cam, pix % J.cam.W, pix / J.cam.W, ro, rd);
+    ray_of<SRC>(J, S, idx, ro, rd);
     if (!ray_setup(J.tr, ro, rd, r, a, hi)) return false;
     const double len = r.s_exit - a;
     const double lo = k == 0 ? a : a + len * (double)k / (double)n;
@@ -850,10 +877,11 @@ __device__ __forceinline__ bool piece_setup(const KJob& J, int pix, double a, do
 }
 
 // Bounds of piece k of n of [a, hi] (as piece_setup cuts it).
-__device__ __forceinline__ void piece_bounds(const KJob& J, int pix, double a, double hi, int k, int n,
-                                             double& lo, double& up) {
+template <int SRC>
+__device__ __forceinline__ void piece_bounds(const KJob& J, const KSplit& S, int idx, double a, double hi, int k,
+                                             int n, double& lo, double& up) {
     double ro[3], rd[3];
-    pixel_ray(J.cam, pix % J.cam.W, pix / J.cam.W, ro, rd);
+    ray_of<SRC>(J, S, idx, ro, rd);
     Ray r;
     const double e = ray_setup(J.tr, ro, rd, r, a, hi) ? r.s_exit : a;
     lo = k == 0 ? a : a + (e - a) * (double)k / (double)n;
@@ -910,29 +938,23 @@ __device__ __forceinline__ int claim_pieces(int32_t* count, int4* __restrict__ i
     return first;
 }
 
-template <typename T, int K, int VEC, int NL, int V>
-__global__ __launch_bounds__(kBlock) void k_render_camera_split(KBatch<1> B, KSplit S) {
-    const int64_t b = xcd_swizzle(blockIdx.x, B.n_blocks);
-    if (b < 0) return;
-    const KJob& J = B.job[0];
+// The first walk of a split render for ray idx (valid: idx names a ray):
+// at most split_steps cells, then the ray is handed on or, if its region of
+// the queue is full, walked to its end here.  Every lane of the wave must
+// call it.
+template <typename T, int K, int VEC, int NL, int V, int SRC>
+__device__ __forceinline__ void first_walk(const KJob& J, const KSplit& S, int idx, bool valid) {
     const KTree& tr = J.tr;
     const KOpts& op = J.op;
-    const int q = (int)b;
-    const int tile = J.tile_begin + (q >> 2), quad = q & 3;
-    const int tx = tile % J.tiles_x, ty = tile / J.tiles_x;
-    const int lane = threadIdx.x;
-    const int px = tx * 16 + (quad & 1) * 8 + (lane & 7);
-    const int py = ty * 16 + (quad >> 1) * 8 + (lane >> 3);
-    const bool valid = (px < J.cam.W) & (py < J.cam.H);
     extern __shared__ int po_stack[];
-    int* stk = po_stack + lane;
-    using Smp = FwdSampler<T, K, VEC, NL, false>;
+    int* stk = po_stack + threadIdx.x;
+    using Smp = FirstSampler<T, K, VEC, NL, V>;
     Smp smp;
     Ray r;
     int want = 0, steps = 0;
     if (valid) {
         double ro[3], rd[3];
-        pixel_ray(J.cam, px, py, ro, rd);
+        ray_of<SRC>(J, S, idx, ro, rd);
         if (ray_setup(tr, ro, rd, r)) {
             const double s_first = r.s;
             fwd_init<T, K, V>(smp, tr, op, r);
@@ -955,7 +977,7 @@ __global__ __launch_bounds__(kBlock) void k_render_camera_split(KBatch<1> B, KSp
             hd.c0 = smp.c0;
             hd.c1 = smp.c1;
             hd.c2 = smp.c2;
-            hd.pix = py * J.cam.W + px;
+            hd.pix = idx;
             hd.pad = 0;
             reinterpret_cast<ContHead*>(S.head)[h] = hd;
             handed = true;
@@ -964,11 +986,35 @@ __global__ __launch_bounds__(kBlock) void k_render_camera_split(KBatch<1> B, KSp
         }
     }
     if (valid && !handed) {
-        const size_t p = (size_t)py * J.cam.W + px;
+        const size_t p = (size_t)idx;
         J.rgb[3 * p + 0] = fmaf(smp.Tl, op.bg[0], smp.c0);
         J.rgb[3 * p + 1] = fmaf(smp.Tl, op.bg[1], smp.c1);
         J.rgb[3 * p + 2] = fmaf(smp.Tl, op.bg[2], smp.c2);
     }
+}
+
+template <typename T, int K, int VEC, int NL, int V>
+__global__ __launch_bounds__(kBlock) void k_render_camera_split(KBatch<1> B, KSplit S) {
+    const int64_t b = xcd_swizzle(blockIdx.x, B.n_blocks);
+    if (b < 0) return;
+    const KJob& J = B.job[0];
+    const int q = (int)b;
+    const int tile = J.tile_begin + (q >> 2), quad = q & 3;
+    const int tx = tile % J.tiles_x, ty = tile / J.tiles_x;
+    const int lane = threadIdx.x;
+    const int px = tx * 16 + (quad & 1) * 8 + (lane & 7);
+    const int py = ty * 16 + (quad >> 1) * 8 + (lane >> 3);
+    const bool valid = (px < J.cam.W) & (py < J.cam.H);
+    first_walk<T, K, VEC, NL, V, 0>(J, S, valid ? py * J.cam.W + px : 0, valid);
+}
+
+template <typename T, int K, int VEC, int NL, int V>
+__global__ __launch_bounds__(kBlock) void k_render_rays_split(KBatch<1> B, KSplit S) {
+    const int64_t b = xcd_swizzle(blockIdx.x, B.n_blocks);
+    if (b < 0) return;
+    const int64_t i = b * kBlock + threadIdx.x;
+    const bool valid = i < S.n_rays;
+    first_walk<T, K, VEC, NL, V, 1>(B.job[0], S, valid ? (int)i : 0, valid);
 }
 
 __global__ void k_zero_i32(int32_t* __restrict__ p, int n) {
@@ -992,13 +1038,13 @@ __device__ __forceinline__ int split_slot(const int32_t* count) {
     return local < n ? region * kSplitRegionSlots + local : -1;
 }
 
-template <typename T, int K, int VEC, int NL, int V>
+template <typename T, int K, int VEC, int NL, int V, int SRC>
 __global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S) {
     const int q = split_slot(S.count);
     const int4 in = q < 0 ? make_int4(-1, 0, -1, 0) : S.info[q];
     const int h = in.x;
     const KJob& J = B.job[0];
-    using Smp = ChunkSampler<T, K, VEC, NL>;
+    using Smp = ChunkSampler<T, K, VEC, NL, V>;
     Smp smp;
     Ray r;
     int want = 0, steps = 0, pix = 0;
@@ -1008,7 +1054,7 @@ __global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S)
         const int mj = in.y;
         const ContHead hd = reinterpret_cast<const ContHead*>(S.head)[h];
         pix = hd.pix;
-        if (piece_setup(J, pix, hd.s, 1e300, mj & 255, mj >> 8, r)) {
+        if (piece_setup<SRC>(J, S, pix, hd.s, 1e300, mj & 255, mj >> 8, r)) {
             const double s_first = r.s;
             fwd_init<T, K, V>(smp, J.tr, J.op, r);
             steps = march<Smp, true>(J.tr, r, min(S.chunk_cap, J.op.max_steps), stk, smp);
@@ -1055,7 +1101,7 @@ __global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S)
     }
 }
 
-template <typename T, int K, int VEC, int NL, int V>
+template <typename T, int K, int VEC, int NL, int V, int SRC>
 __global__ __launch_bounds__(kBlock) void k_render_subchunks(KBatch<1> B, KSplit S) {
     const int q = split_slot(S.count2);
     if (q < 0) return;
@@ -1065,10 +1111,10 @@ __global__ __launch_bounds__(kBlock) void k_render_subchunks(KBatch<1> B, KSplit
     const int mj = in.y;
     const SubHead sh = reinterpret_cast<const SubHead*>(S.head2)[h];
     const KJob& J = B.job[0];
-    using Smp = ChunkSampler<T, K, VEC, NL>;
+    using Smp = ChunkSampler<T, K, VEC, NL, V>;
     Smp smp;
     Ray r;
-    if (piece_setup(J, sh.pix, sh.lo, sh.hi, mj & 255, mj >> 8, r)) {
+    if (piece_setup<SRC>(J, S, sh.pix, sh.lo, sh.hi, mj & 255, mj >> 8, r)) {
         fwd_init<T, K, V>(smp, J.tr, J.op, r);
         extern __shared__ int po_stack[];
         march(J.tr, r, J.op.max_steps, po_stack + threadIdx.x, smp);
@@ -1089,19 +1135,19 @@ __global__ __launch_bounds__(kBlock) void k_render_subchunks(KBatch<1> B, KSplit
 // of [a, hi]; a chunk whose remainder was handed on (o.n_sub > 0) ends where
 // its remainder begins.  Returns true when early stopping ends the ray in
 // this piece.
-template <typename T, int K, int VEC, int NL, int V>
+template <typename T, int K, int VEC, int NL, int V, int SRC>
 __device__ __forceinline__ bool join_piece(const KJob& J, const KSplit& S, int pix, double a, double hi, int k,
                                            int n, const PieceOut& o, float& Tp, float (&c)[3]) {
     if (o.Tlast >= 0.0f && Tp * o.Tlast < J.op.stop_T) {
         // the walk stops inside this piece: walk it again from Tp
         double lo, up;
-        piece_bounds(J, pix, a, hi, k, n, lo, up);
+        piece_bounds<SRC>(J, S, pix, a, hi, k, n, lo, up);
         if (o.n_sub > 0) up = reinterpret_cast<const SubHead*>(S.head2)[o.sub].lo;
-        using Smp = ChunkSampler<T, K, VEC, NL>;
+        using Smp = ChunkSampler<T, K, VEC, NL, V>;
         Smp smp;
         smp.Tl = Tp;
         Ray r;
-        if (piece_setup(J, pix, lo, up, 0, 1, r)) {
+        if (piece_setup<SRC>(J, S, pix, lo, up, 0, 1, r)) {
             fwd_init<T, K, V>(smp, J.tr, J.op, r);
             extern __shared__ int po_stack[];
             march(J.tr, r, J.op.max_steps, po_stack + threadIdx.x, smp);
@@ -1120,7 +1166,7 @@ __device__ __forceinline__ bool join_piece(const KJob& J, const KSplit& S, int p
     return false;
 }
 
-template <typename T, int K, int VEC, int NL, int V>
+template <typename T, int K, int VEC, int NL, int V, int SRC>
 __global__ __launch_bounds__(kBlock) void k_render_join(KBatch<1> B, KSplit S) {
     const int q = split_slot(S.count);
     if (q < 0) return;
@@ -1139,7 +1185,7 @@ __global__ __launch_bounds__(kBlock) void k_render_join(KBatch<1> B, KSplit S) {
     for (int j = 0; j < m && !done; ++j) {
         const PieceOut o = part[qj];
         qj = S.info[qj].z;
-        done = join_piece<T, K, VEC, NL, V>(J, S, hd.pix, hd.s, 1e300, j, m, o, Tp, c);
+        done = join_piece<T, K, VEC, NL, V, SRC>(J, S, hd.pix, hd.s, 1e300, j, m, o, Tp, c);
         if (o.n_sub > 0 && !done) {
             // the remainder's sub-chunks (bounds read only to walk one again)
             double slo = 0.0, shi = 0.0;
@@ -1152,7 +1198,7 @@ __global__ __launch_bounds__(kBlock) void k_render_join(KBatch<1> B, KSplit S) {
                     slo = sh.lo;
                     shi = sh.hi;
                 }
-                done = join_piece<T, K, VEC, NL, V>(J, S, hd.pix, slo, shi, k, o.n_sub, o2, Tp, c);
+                done = join_piece<T, K, VEC, NL, V, SRC>(J, S, hd.pix, slo, shi, k, o.n_sub, o2, Tp, c);
             }
         }
     }
@@ -1511,9 +1557,8 @@ hipError_t camera_t(const po_tree* t, int n_jobs, KJob* jobs, int n_blocks, int 
     return hipGetLastError();
 }
 
-template <typename T, int K>
-hipError_t camera_split_t(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
-                          hipStream_t s) {
+template <typename T, int K, int SRC>
+hipError_t split_t(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S, hipStream_t s) {
     using P = Plan<T, K>;
     KBatch<1> B;
     B.job[0] = job;
@@ -1527,11 +1572,24 @@ hipError_t camera_split_t(const po_tree* t, const KJob& job, int n_blocks, int v
     const bool fast = use_fast<T, K>(t);
 #define PO_SPLIT(VEC_, NL_, V_)                                                                        \
     do {                                                                                              \
-        hipLaunchKernelGGL((k_render_camera_split<T, K, VEC_, NL_, V_>), g1, blk, lds, s, B, S);     \
-        hipLaunchKernelGGL((k_render_chunks<T, K, VEC_, NL_, V_>), g2, blk, lds, s, B, S);           \
-        hipLaunchKernelGGL((k_render_subchunks<T, K, VEC_, NL_, V_>), g2, blk, lds, s, B, S);        \
-        hipLaunchKernelGGL((k_render_join<T, K, VEC_, NL_, V_>), g2, blk, lds, s, B, S);             \
+        if constexpr (SRC == 0)                                                                       \
+            hipLaunchKernelGGL((k_render_camera_split<T, K, VEC_, NL_, V_>), g1, blk, lds, s, B, S);  \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_render_rays_split<T, K, VEC_, NL_, V_>), g1, blk, lds, s, B, S);    \
+        hipLaunchKernelGGL((k_render_chunks<T, K, VEC_, NL_, V_, SRC>), g2, blk, lds, s, B, S);      \
+        hipLaunchKernelGGL((k_render_subchunks<T, K, VEC_, NL_, V_, SRC>), g2, blk, lds, s, B, S);   \
+        hipLaunchKernelGGL((k_render_join<T, K, VEC_, NL_, V_, SRC>), g2, blk, lds, s, B, S);        \
     } while (0)
+    if constexpr (std::is_same_v<T, __half>) {
+        if (variant == PO_FWD_CB) {
+            using Q = CbPlan<K>;
+            if (use_fast_cb<K>(t))
+                PO_SPLIT(Q::FAST_VEC, Q::FAST_NL, PO_FWD_CB);
+            else
+                PO_SPLIT(4, Q::GEN_NL, PO_FWD_CB);
+            return hipGetLastError();
+        }
+    }
     if (variant == PO_FWD_SG) {
         if (fast)
             PO_SPLIT(P::FAST_VEC, P::FAST_NL, PO_FWD_SG);
@@ -1602,9 +1660,29 @@ hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, i
 hipError_t po_launch_camera_split(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
                                   hipStream_t s) {
     if (t->desc.dtype == PO_F32) {
-        PO_DISPATCH_K(t->K, (camera_split_t<float, KK>(t, job, n_blocks, variant, S, s)));
+        PO_DISPATCH_K(t->K, (split_t<float, KK, 0>(t, job, n_blocks, variant, S, s)));
     } else {
-        PO_DISPATCH_K(t->K, (camera_split_t<__half, KK>(t, job, n_blocks, variant, S, s)));
+        PO_DISPATCH_K(t->K, (split_t<__half, KK, 0>(t, job, n_blocks, variant, S, s)));
+    }
+}
+
+hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
+                                float* rgb, const KSplit& S0, hipStream_t s) {
+    KJob job;
+    std::memset(&job, 0, sizeof job);
+    job.tr = t->kt;
+    job.op = op;
+    job.rgb = rgb;
+    KSplit S = S0;
+    S.ray_o = o;
+    S.ray_d = d;
+    S.n_rays = n;
+    const int n_blocks = (int)((n + kBlock - 1) / kBlock);
+    const int variant = po_fwd_variant(op, nullptr, t->kt);
+    if (t->desc.dtype == PO_F32) {
+        PO_DISPATCH_K(t->K, (split_t<float, KK, 1>(t, job, n_blocks, variant, S, s)));
+    } else {
+        PO_DISPATCH_K(t->K, (split_t<__half, KK, 1>(t, job, n_blocks, variant, S, s)));
     }
 }
 

@@ -260,3 +260,65 @@ def test_split_max_depth(po):
     _say(f"depth 15: split vs oracle max {err.max():.2e}")
     assert err.max() <= TOL
     assert po.device_errors() == 0
+
+
+@pytest.mark.parametrize("stop_T", [0.0, 1e-4])
+def test_split_ray_list(po, fog, stop_T):
+    # ray-list renders of >= 2^18 rays are split too; the viewer variant
+    # (aux outputs) walks them in one pass with the same colours
+    import torch
+
+    s, tree, ot = fog
+    cam, pose = _cam(po, 512, 512, seed=3)
+    f32 = [float(np.float32(v)) for v in (cam.fx, cam.fy, cam.cx, cam.cy)]
+    o, d = oracle.camera_rays(np.asarray(pose, np.float32).astype(np.float64), 512, 512, *f32)
+    o2, d2 = scenes.random_rays(20000, 37, radius=2.5, spread=0.9)
+    o = np.concatenate([o, o2]).astype(np.float32)
+    d = np.concatenate([d, d2]).astype(np.float32)
+    n = len(o)
+    _say(f"split ray list, {n} rays, stop_T {stop_T}")
+    og, dg = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
+    rgb = po.render_rays(tree, og, dg, stop_T=stop_T).cpu().numpy()
+    one, aux = po.render_rays(tree, og, dg, stop_T=stop_T, aux=True)
+    one, aux = one.cpu().numpy(), aux.cpu().numpy()
+    assert (aux[:, 2] > 32).sum() > 60000
+    dd = np.abs(rgb - one).max(1)
+    _say(f"ray list: split vs one pass max {dd.max():.2e}, above 1e-5: {(dd > 1e-5).sum()}")
+    assert np.mean(dd > 1e-5) <= 1e-4 and dd.max() <= stop_T + 1e-5
+    # one ray fewer than the split size renders in one pass, bit-identical
+    small = po.render_rays(tree, og[:(1 << 18) - 1], dg[:(1 << 18) - 1], stop_T=stop_T).cpu().numpy()
+    assert np.array_equal(small, one[:(1 << 18) - 1])
+    rng = np.random.default_rng(31)
+    idx = np.unique(np.concatenate([rng.choice(n, 2000, replace=False), np.argsort(-aux[:, 2])[:300]]))
+    ref, _, _, _ = ot.render_rays(o[idx].astype(np.float64), d[idx].astype(np.float64), gamma=stop_T)
+    err = np.abs(rgb[idx] - ref).max(1)
+    _say(f"ray list: split vs oracle max {err.max():.2e}")
+    assert err.max() <= TOL
+    assert po.device_errors() == 0
+
+
+def test_split_codebook(po, fog):
+    # codebook leaves (App. B.2) through the split render: the oracle renders
+    # the leaves its own codebooks decode to
+    s, _, _ = fog
+    M = 256
+    tree = po.Tree.from_cells_codebook(s["depth"], s["sh_degree"], s["cells"], s["sigma"], s["sh"], M, s["center"],
+                                       s["half"])
+    cam, pose = _cam(po, 288, 256, seed=17)
+    _say("split render, codebook tree")
+    img = po.render_camera(tree, cam, stop_T=1e-4).cpu().numpy()
+    one, _ = _one_pass(po, tree, cam, 1e-4)
+    d = np.abs(img - one).max(-1)
+    _say(f"codebook: split vs one pass max {d.max():.2e}")
+    assert np.mean(d > 1e-5) <= 1e-4 and d.max() <= 1e-4 + 1e-5
+    idx_, books = oracle.codebook(np.asarray(s["sh"], np.float32), M)
+    sig16 = np.asarray(s["sigma"], np.float32).astype(np.float16).astype(np.float64)
+    ot = oracle.OracleTree(s["depth"], s["sh_degree"], s["center"], s["half"], s["cells"], sig16,
+                           oracle.codebook_decode(idx_, books))
+    rng = np.random.default_rng(37)
+    idx = rng.choice(288 * 256, 1500, replace=False)
+    ref, _ = _oracle_pixels(ot, cam, pose, idx, 1e-4)
+    err = np.abs(img.reshape(-1, 3)[idx] - ref).max(1)
+    _say(f"codebook: split vs oracle max {err.max():.2e}")
+    assert err.max() <= TOL
+    assert po.device_errors() == 0
