@@ -345,6 +345,15 @@ po_status po_leaf_weights(const po_tree* t, const po_camera* cam, const po_rende
 po_status po_tree_leaf_cells(const po_tree_desc* desc, int64_t n_nodes, const int32_t* h_child, int64_t n_leaves,
                              int32_t* h_cells);
 
+/* --------------------------------------------------------------- resources
+ * po_release_queues: frees the work queues of the split render (one per
+ * device and stream that rendered in pieces; see po_render_camera) after
+ * waiting for all work on each of their devices.  Later split renders make
+ * new ones.  Call it from one thread while no render is being issued.
+ * Errors: PO_ERR_DEVICE (a wait or free failed; the remaining queues are
+ * still released). */
+po_status po_release_queues(void);
+
 /* ----------------------------------------------------------------- errors
  * Device error counter: malformed child entries met and traversal step caps
  * hit, summed over all kernels since load or the last reset.  Reading

@@ -78,6 +78,7 @@ _SIGS = {
     "po_tree_leaf_cells": [ctypes.POINTER(po_tree_desc), _I64, _P, _I64, _P],
     "po_device_errors": [ctypes.POINTER(_I64)],
     "po_device_errors_reset": [],
+    "po_release_queues": [],
 }
 EXPORTS = list(_SIGS) + ["po_status_str", "po_last_error", "po_version"]
 

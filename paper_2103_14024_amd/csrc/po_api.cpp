@@ -701,6 +701,24 @@ po_status po_leaf_weights(const po_tree* t, const po_camera* cam, const po_rende
     return ok();
 }
 
+po_status po_release_queues(void) {
+    std::lock_guard<std::mutex> lk(g_split_mu);
+    if (g_split.empty()) return ok();
+    hipError_t first = hipSuccess;
+    int cur = 0;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    for (auto& kv : g_split) {
+        hipError_t e = hipSetDevice(kv.first.first);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipFree(kv.second);
+        if (e != hipSuccess && first == hipSuccess) first = e;
+    }
+    g_split.clear();
+    if (have_cur) (void)hipSetDevice(cur);
+    if (first != hipSuccess) return device_fail(first, "releasing the split-render queues");
+    return ok();
+}
+
 po_status po_device_errors(int64_t* count) {
     if (!count) return fail(PO_ERR_INVALID, "count is NULL");
     unsigned long long v = 0;

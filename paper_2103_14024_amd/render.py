@@ -236,3 +236,8 @@ def device_errors() -> int:
 
 def reset_device_errors() -> None:
     L.call("po_device_errors_reset")
+
+
+def release_queues() -> None:
+    """Frees the split-render work queues (waits for the devices first)."""
+    L.call("po_release_queues")

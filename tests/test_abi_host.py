@@ -31,6 +31,11 @@ def test_exports_every_declared_symbol(lib):
     assert L.version().startswith("plenoctree-mi355x")
 
 
+def test_release_queues_without_any(lib):
+    # nothing was rendered in pieces: nothing to free, no device touched
+    L.call("po_release_queues")
+
+
 def test_status_strings(lib):
     for s in range(6):
         assert L.status_str(s)

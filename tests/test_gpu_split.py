@@ -194,6 +194,17 @@ def test_split_repeated_and_small(po, fog):
         b = po.render_camera(tree, cam, stop_T=1e-4)
         torch.cuda.synchronize()
         assert torch.equal(a, b)
+    # the queues can be released; the next split render makes new ones
+    po.release_queues()
+    b = po.render_camera(tree, cam, stop_T=1e-4)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    # a second stream gets its own queue
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        c = po.render_camera(tree, cam, stop_T=1e-4, stream=st)
+    st.synchronize()
+    assert torch.equal(a, c)
     assert po.device_errors() == 0
 
 
