@@ -201,8 +201,9 @@ po_status po_tree_destroy(po_tree* t);
  * d_aux[n][4].  The colour is sum_i T_i (1 - exp(-sigma_i delta_i)) c_i +
  * T_N bg over the data segments met before the early stop (Sec. 3 eqn:quad,
  * App. B.3), c_i = sigmoid(sum_k sh[leaf][ch][k] Y_k(d)) (Sec. 4.1).
- * Lists of at least 2^18 rays without viewer options are rendered in pieces
- * as po_render_camera describes (same queue, same equality up to rounding).
+ * Lists of at least 65536 rays without viewer options are rendered in
+ * pieces as po_render_camera describes (same queue, same equality up to
+ * rounding).
  * Errors: PO_ERR_INVALID (NULL tree/opts/arrays with n > 0, n < 0, bad
  * options), PO_ERR_DEVICE (launch failure). */
 po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, const float* d_dirs,
@@ -246,6 +247,12 @@ po_status po_camera_rays(const po_camera* cam, float* d_origins, float* d_dirs, 
  * rule through the sigmoid and the SH basis).  Several rays may hit one
  * leaf, so accumulation uses float atomics and its summation order is not
  * deterministic.  Zero the outputs first when a fresh gradient is wanted.
+ * Batches of at least 65536 rays are differentiated in pieces: the rays
+ * walked for a bounded number of cells are handed on as pieces whose
+ * transmittance and colour prefix in front come from a forward pass over the
+ * pieces, then every piece before the early stop is differentiated in
+ * parallel (a cell cut between two pieces is two segments whose gradients add
+ * up to the cell's).  Uses the work queue of po_render_camera.
  * Errors: PO_ERR_INVALID, PO_ERR_UNSUPPORTED (tree not PO_F32, or viewer
  * options sh_off / clip set), PO_ERR_DEVICE. */
 po_status po_render_rays_backward(const po_tree* t, int64_t n, const float* d_origins,

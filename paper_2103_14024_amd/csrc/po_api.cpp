@@ -47,10 +47,17 @@ bool finite(float v) { return std::isfinite(v); }
 // Camera renders of at least kSplitMinPixels pixels and ray-list renders of
 // at least kSplitMinRays rays use the split render.  Its five launches each
 // end with their own longest walk, which outweighs the shorter critical path
-// for small launches (65536 random training rays of a depth-8 tree: 321 us
-// split against 297 us in one pass).
+// for small launches.
 constexpr int64_t kSplitMinPixels = 1 << 16;
-constexpr int64_t kSplitMinRays = 1 << 18;
+#ifndef PO_SPLIT_MIN_RAYS
+#define PO_SPLIT_MIN_RAYS (1 << 16)
+#endif
+constexpr int64_t kSplitMinRays = PO_SPLIT_MIN_RAYS;
+// Backward passes of at least this many rays run in pieces.
+#ifndef PO_SPLIT_MIN_BACKWARD
+#define PO_SPLIT_MIN_BACKWARD (1 << 16)
+#endif
+constexpr int64_t kSplitMinBackward = PO_SPLIT_MIN_BACKWARD;
 
 // Work queues of the split camera render, one per (device, stream), made on
 // first use and kept until the process ends.
@@ -588,8 +595,15 @@ po_status po_render_rays_backward(const po_tree* t, int64_t n, const float* d_or
     if (n > (1ll << 40)) return fail(PO_ERR_INVALID, "n = %lld too large", (long long)n);
     if (!d_origins || !d_dirs || !d_rgb_fwd || !d_grad_rgb || !d_grad_sigma || !d_grad_sh)
         return fail(PO_ERR_INVALID, "NULL array");
-    hipError_t e = po_launch_backward(t, n, d_origins, d_dirs, kopts(t, opts), d_rgb_fwd, d_grad_rgb, d_grad_sigma,
-                                      d_grad_sh, (hipStream_t)stream);
+    const KOpts k = kopts(t, opts);
+    KSplit S;
+    hipError_t e;
+    if (n >= kSplitMinBackward && n < (1ll << 31) && k.max_steps > PO_SPLIT_STEPS && split_queue(stream, &S))
+        e = po_launch_backward_split(t, n, d_origins, d_dirs, k, d_rgb_fwd, d_grad_rgb, d_grad_sigma, d_grad_sh, S,
+                                     (hipStream_t)stream);
+    else
+        e = po_launch_backward(t, n, d_origins, d_dirs, k, d_rgb_fwd, d_grad_rgb, d_grad_sigma, d_grad_sh,
+                               (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "backward launch");
     return ok();
 }

@@ -96,6 +96,23 @@ constexpr int kSplitMaxChunks = 16;
 #ifndef PO_SPLIT_UB_FRAC
 #define PO_SPLIT_UB_FRAC 0.2f
 #endif
+// piece sizes of ray-list renders of fewer than PO_RAYS_SMALL rays, and of
+// the backward
+#ifndef PO_RAYS_SMALL
+#define PO_RAYS_SMALL (1 << 18)
+#endif
+#ifndef PO_RAYS_CHUNK_STEPS
+#define PO_RAYS_CHUNK_STEPS 8
+#endif
+#ifndef PO_RAYS_CHUNK_CAP
+#define PO_RAYS_CHUNK_CAP 16
+#endif
+#ifndef PO_BWD_CHUNK_STEPS
+#define PO_BWD_CHUNK_STEPS 12
+#endif
+#ifndef PO_BWD_CHUNK_CAP
+#define PO_BWD_CHUNK_CAP 16
+#endif
 struct KSplit {
     int32_t* count;        // [kSplitRegions] chunk slots claimed (may exceed the region); count2 follows
     int32_t* count2;       // [kSplitRegions] sub-chunk slots claimed
@@ -152,6 +169,11 @@ hipError_t po_launch_camera_split(const po_tree* t, const KJob& job, int n_block
 // the queue must not be in use by work on another stream.
 hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
                                 float* rgb, const KSplit& S, hipStream_t s);
+// Backward of n rays (n < 2^31, float32 tree) in pieces: the first walk,
+// the forward of the pieces, their prefixes, then the backward of the pieces.
+hipError_t po_launch_backward_split(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
+                                    const float* rgb_fwd, const float* grad, float* gsig, float* gsh,
+                                    const KSplit& S, hipStream_t s);
 hipError_t po_launch_camera_rays(const KCam& cam, float* o, float* d, hipStream_t s);
 // Visibility filter: mode 0 alpha, 1 contribution; weight[n_leaves] raised in place, alpha[H*W] or nullptr.
 hipError_t po_launch_leaf_weights(const po_tree* t, const KCam& cam, const KOpts& op, int mode, float* weight,

@@ -1022,18 +1022,14 @@ __global__ void k_zero_i32(int32_t* __restrict__ p, int n) {
     if (i < n) p[i] = 0;
 }
 
-// Queue slot of this thread, or -1 beyond its region's claimed slots.
-// Workgroup b takes region b % kSplitRegions, so that the workgroups with
-// work come first in dispatch order and each region stays on the XCD whose
-// workgroups filled it (b % 8 is the XCD).
-__device__ __forceinline__ int split_slot(const int32_t* count) {
-#ifdef PO_REGION_MAJOR
-    const int region = (int)(blockIdx.x % kSplitRegions);
-    const int local = (int)(blockIdx.x / kSplitRegions) * kBlock + (int)threadIdx.x;
-#else
-    const int region = (int)(blockIdx.x / (kSplitRegionSlots / kBlock));
-    const int local = (int)(blockIdx.x % (kSplitRegionSlots / kBlock)) * kBlock + (int)threadIdx.x;
-#endif
+// Queue slot of this thread (workgroup blockIdx.x - first), or -1 beyond its
+// region's claimed slots.  Consecutive workgroups take consecutive slots of a
+// region (faster than interleaving the regions: 735 against 1035 us per
+// depth-9 frame).
+__device__ __forceinline__ int split_slot(const int32_t* count, int first = 0) {
+    const int b = (int)blockIdx.x - first;
+    const int region = b / (kSplitRegionSlots / kBlock);
+    const int local = (b % (kSplitRegionSlots / kBlock)) * kBlock + (int)threadIdx.x;
     const int n = min(count[region], kSplitRegionSlots);
     return local < n ? region * kSplitRegionSlots + local : -1;
 }
@@ -1343,6 +1339,195 @@ __global__ __launch_bounds__(kBlock) void k_backward(KTree tr, int64_t n, int64_
     march(tr, r, op.max_steps, po_stack + threadIdx.x, smp);
 }
 
+// ---------------------------------------------------------------------------
+// Split backward.  The gradient of a ray's pieces needs, at the start of each
+// piece, the transmittance T and the colour prefix P = sum of w_k c_k of
+// everything in front of it (App. B.3: dC/dsigma_i = delta_i (c_i T_{i+1} -
+// (C - P_i)), dC/dk = w_i c_i (1 - c_i) Y).  A piece that cuts a cell is a
+// segment of its own: the two parts' gradients add up to the whole cell's.
+//   k_backward_split      the backward of the first split_steps cells of
+//                         every ray, which then hands the rest on as chunks
+//                         (head state: s, T, P);
+//   k_render_chunks,
+//   k_render_subchunks    the forward of the pieces (colour and transmittance
+//                         from T = 1), as in the split render;
+//   k_piece_prefix        per ray, front to back: T and P at the start of
+//                         every piece and which pieces lie before the early
+//                         stop (the piece holding it walked again, as in the
+//                         join), written over the piece's forward result;
+//   k_backward_pieces     the backward of every piece before the stop, from
+//                         its T and P (chunks, then sub-chunks).
+// ---------------------------------------------------------------------------
+template <int K, class Smp>
+__device__ __forceinline__ void bwd_init(Smp& smp, const KTree& tr, const KOpts& op, const Ray& r, size_t i,
+                                         const float* __restrict__ rgb_fwd, const float* __restrict__ grad,
+                                         float* gsig, float* gsh, float* sprod, int* sleaf) {
+    smp.g0 = grad[3 * i];
+    smp.g1 = grad[3 * i + 1];
+    smp.g2 = grad[3 * i + 2];
+    smp.C0 = rgb_fwd[3 * i];
+    smp.C1 = rgb_fwd[3 * i + 1];
+    smp.C2 = rgb_fwd[3 * i + 2];
+    smp.sig = raw_rsrc(tr.sigma, tr.sigma_bytes);
+    smp.shb = raw_rsrc(tr.sh, tr.sh_bytes);
+    smp.sig_end = tr.sigma_bytes;
+    smp.sh_end = tr.sh_bytes;
+    smp.rec_bytes = (uint32_t)tr.stride * 4u;
+    smp.stride = tr.stride;
+    smp.stopT = op.stop_T;
+    smp.gsig = gsig;
+    smp.gsh = gsh;
+    smp.sprod = sprod;
+    smp.sleaf = sleaf;
+    colour_basis<K>(tr, r.dn[0], r.dn[1], r.dn[2], smp.Y);
+}
+
+template <int K, int VEC, int NL>
+__global__ __launch_bounds__(kBlock) void k_backward_split(KBatch<1> B, KSplit S, const float* __restrict__ rgb_fwd,
+                                                           const float* __restrict__ grad, float* __restrict__ gsig,
+                                                           float* __restrict__ gsh) {
+    const int64_t b = xcd_swizzle(blockIdx.x, B.n_blocks);
+    if (b < 0) return;
+    const int64_t i = b * kBlock + threadIdx.x;
+    const KJob& J = B.job[0];
+    const KTree& tr = J.tr;
+    using Smp = BwdSampler<K, VEC, NL>;
+    Smp smp;
+    __shared__ float s_prod[kBlock * Smp::SW];
+    __shared__ int s_leaf[kBlock];
+    extern __shared__ int po_stack[];
+    int* stk = po_stack + threadIdx.x;
+    Ray r;
+    int want = 0, steps = 0;
+    bool live = false;
+    if (i < S.n_rays) {
+        double ro[3], rd[3];
+        ray_of<1>(J, S, (int)i, ro, rd);
+        if (ray_setup(tr, ro, rd, r)) {
+            bwd_init<K>(smp, tr, J.op, r, (size_t)i, rgb_fwd, grad, gsig, gsh, s_prod, s_leaf);
+            live = !(smp.g0 == 0.0f && smp.g1 == 0.0f && smp.g2 == 0.0f);
+        }
+    }
+    if (live) {
+        const double s_first = r.s;
+        steps = march<Smp, true>(tr, r, min(S.split_steps, J.op.max_steps), stk, smp);
+        if (r.more) {
+            if (steps >= J.op.max_steps)
+                atomicAdd(&g_po_errors, 1ull);
+            else
+                want = pieces_wanted(r, s_first, steps, S);
+        }
+    }
+    const int h = claim_pieces(S.count, S.info, (int)(blockIdx.x % kSplitRegions), want);
+    if (want > 0) {
+        if (h >= 0) {
+            ContHead hd;
+            hd.s = r.s;
+            hd.T = smp.Tl;
+            hd.c0 = smp.P0;
+            hd.c1 = smp.P1;
+            hd.c2 = smp.P2;
+            hd.pix = (int)i;
+            hd.pad = 0;
+            reinterpret_cast<ContHead*>(S.head)[h] = hd;
+        } else {
+            march<Smp>(tr, r, J.op.max_steps - steps, stk, smp);  // region full: finish here
+        }
+    }
+}
+
+// Prefix of one piece: its forward result o is replaced by (P, T) in front
+// of it and whether it lies before the early stop (Tlast 1) or not (-1).
+template <int K, int VEC, int NL, int V>
+__device__ __forceinline__ void prefix_piece(const KJob& J, const KSplit& S, int pix, double a, double hi, int k,
+                                             int n, PieceOut* rec, float& Tp, float (&P)[3], bool& done) {
+    const PieceOut o = *rec;
+    PieceOut w = o;
+    w.c0 = P[0];
+    w.c1 = P[1];
+    w.c2 = P[2];
+    w.T = Tp;
+    w.Tlast = done ? -1.0f : 1.0f;
+    *rec = w;
+    if (!done) done = join_piece<float, K, VEC, NL, V, 1>(J, S, pix, a, hi, k, n, o, Tp, P);
+}
+
+template <int K, int VEC, int NL, int V>
+__global__ __launch_bounds__(kBlock) void k_piece_prefix(KBatch<1> B, KSplit S) {
+    const int q = split_slot(S.count);
+    if (q < 0) return;
+    const int4 in = S.info[q];
+    if (in.x != q) return;
+    const int m = in.y >> 8;
+    const ContHead hd = reinterpret_cast<const ContHead*>(S.head)[q];
+    const KJob& J = B.job[0];
+    PieceOut* part = reinterpret_cast<PieceOut*>(S.part);
+    PieceOut* part2 = reinterpret_cast<PieceOut*>(S.part2);
+    const SubHead* head2 = reinterpret_cast<const SubHead*>(S.head2);
+    float Tp = hd.T;
+    float P[3] = {hd.c0, hd.c1, hd.c2};
+    bool done = false;
+    int qj = q;
+    for (int j = 0; j < m; ++j) {
+        const int n_sub = part[qj].n_sub, sub = part[qj].sub;
+        prefix_piece<K, VEC, NL, V>(J, S, hd.pix, hd.s, 1e300, j, m, part + qj, Tp, P, done);
+        if (n_sub > 0) {
+            const SubHead sh = head2[sub];
+            int qk = sub;
+            for (int k = 0; k < n_sub; ++k) {
+                prefix_piece<K, VEC, NL, V>(J, S, hd.pix, sh.lo, sh.hi, k, n_sub, part2 + qk, Tp, P, done);
+                qk = S.info2[qk].z;
+            }
+        }
+        qj = S.info[qj].z;
+    }
+}
+
+// The first kSplitSlots / kBlock workgroups take the walked parts of the
+// chunks, the others the sub-chunks: the two sets are independent once their
+// prefixes are known, so one launch overlaps their tails.
+template <int K, int VEC, int NL>
+__global__ __launch_bounds__(kBlock) void k_backward_pieces(KBatch<1> B, KSplit S, const float* __restrict__ rgb_fwd,
+                                                            const float* __restrict__ grad, float* __restrict__ gsig,
+                                                            float* __restrict__ gsh) {
+    const bool sub = blockIdx.x >= (unsigned)(kSplitSlots / kBlock);
+    const int q = split_slot(sub ? S.count2 : S.count, sub ? kSplitSlots / kBlock : 0);
+    if (q < 0) return;
+    const int4 in = (sub ? S.info2 : S.info)[q];
+    if (in.x < 0) return;
+    const PieceOut o = reinterpret_cast<const PieceOut*>(sub ? S.part2 : S.part)[q];
+    if (o.Tlast < 0.0f) return;  // behind the early stop
+    const KJob& J = B.job[0];
+    const int k = in.y & 255, n = in.y >> 8;
+    int idx;
+    Ray r;
+    bool ok;
+    if (sub) {
+        const SubHead sh = reinterpret_cast<const SubHead*>(S.head2)[in.x];
+        idx = sh.pix;
+        ok = piece_setup<1>(J, S, idx, sh.lo, sh.hi, k, n, r);
+    } else {
+        const ContHead hd = reinterpret_cast<const ContHead*>(S.head)[in.x];
+        idx = hd.pix;
+        double lo, up;
+        piece_bounds<1>(J, S, idx, hd.s, 1e300, k, n, lo, up);
+        if (o.n_sub > 0) up = reinterpret_cast<const SubHead*>(S.head2)[o.sub].lo;
+        ok = piece_setup<1>(J, S, idx, lo, up, 0, 1, r);
+    }
+    if (!ok) return;
+    using Smp = ChunkOf<BwdSampler<K, VEC, NL>>;
+    Smp smp;
+    __shared__ float s_prod[kBlock * BwdSampler<K, VEC, NL>::SW];
+    __shared__ int s_leaf[kBlock];
+    bwd_init<K>(smp, J.tr, J.op, r, (size_t)idx, rgb_fwd, grad, gsig, gsh, s_prod, s_leaf);
+    smp.Tl = o.T;
+    smp.P0 = o.c0;
+    smp.P1 = o.c1;
+    smp.P2 = o.c2;
+    extern __shared__ int po_stack[];
+    march(J.tr, r, J.op.max_steps, po_stack + threadIdx.x, smp);
+}
+
 // Visibility filter of the conversion (Sec. 4.2, "Filtering"): alpha
 // renders of a camera that raise every leaf's weight to the largest weight
 // of a segment in it, MODE 0 the segment's alpha 1 - exp(-sigma delta),
@@ -1606,6 +1791,51 @@ hipError_t split_t(const po_tree* t, const KJob& job, int n_blocks, int variant,
 }
 
 template <int K>
+hipError_t backward_split_t(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
+                            const float* rgb_fwd, const float* grad, float* gsig, float* gsh, const KSplit& S0,
+                            hipStream_t s) {
+    using P = Plan<float, K>;
+    KBatch<1> B;
+    std::memset(&B, 0, sizeof B);
+    B.job[0].tr = t->kt;
+    B.job[0].op = op;
+    B.n_jobs = 1;
+    B.n_blocks = (int)((n + kBlock - 1) / kBlock);
+    KSplit S = S0;
+    S.ray_o = o;
+    S.ray_d = d;
+    S.n_rays = n;
+    hipLaunchKernelGGL(k_zero_i32, dim3(2), dim3(kSplitRegions), 0, s, S.count, 2 * kSplitRegions);
+    dim3 g1((unsigned)grid_for(B.n_blocks)), g2((unsigned)(kSplitSlots / kBlock)), g3(2u * g2.x), blk(kBlock);
+    const size_t lds = stack_bytes(t->kt.depth);
+    const bool sg = t->kt.lobes != nullptr;
+    // smaller pieces than the forward's: a backward step costs more (the
+    // gradient atomics), and a batch of rays fills the chip less than a frame
+    S.chunk_steps = PO_BWD_CHUNK_STEPS;
+    S.chunk_cap = PO_BWD_CHUNK_CAP;
+#define PO_BSPLIT(VEC_, NL_)                                                                                    \
+    do {                                                                                                       \
+        hipLaunchKernelGGL((k_backward_split<K, VEC_, NL_>), g1, blk, lds, s, B, S, rgb_fwd, grad, gsig, gsh); \
+        if (sg) {                                                                                              \
+            hipLaunchKernelGGL((k_render_chunks<float, K, VEC_, NL_, PO_FWD_SG, 1>), g2, blk, lds, s, B, S);   \
+            hipLaunchKernelGGL((k_render_subchunks<float, K, VEC_, NL_, PO_FWD_SG, 1>), g2, blk, lds, s, B, S); \
+            hipLaunchKernelGGL((k_piece_prefix<K, VEC_, NL_, PO_FWD_SG>), g2, blk, lds, s, B, S);              \
+        } else {                                                                                               \
+            hipLaunchKernelGGL((k_render_chunks<float, K, VEC_, NL_, PO_FWD_SH, 1>), g2, blk, lds, s, B, S);   \
+            hipLaunchKernelGGL((k_render_subchunks<float, K, VEC_, NL_, PO_FWD_SH, 1>), g2, blk, lds, s, B, S); \
+            hipLaunchKernelGGL((k_piece_prefix<K, VEC_, NL_, PO_FWD_SH>), g2, blk, lds, s, B, S);              \
+        }                                                                                                      \
+        hipLaunchKernelGGL((k_backward_pieces<K, VEC_, NL_>), g3, blk, lds, s, B, S, rgb_fwd, grad, gsig, gsh);    \
+    } while (0)
+    if (use_fast<float, K>(t))
+        PO_BSPLIT(P::FAST_VEC, P::FAST_NL);
+    else
+        PO_BSPLIT(4, P::GEN_NL);
+#undef PO_BSPLIT
+    return hipGetLastError();
+}
+
+template <int K>
 hipError_t backward_t(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
                       const float* rgb_fwd, const float* grad, float* gsig, float* gsh, hipStream_t s) {
     using P = Plan<float, K>;
@@ -1677,6 +1907,13 @@ hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, con
     S.ray_o = o;
     S.ray_d = d;
     S.n_rays = n;
+    // a batch of rays below a frame's size fills the chip less: smaller pieces
+    // (65536 random rays of the depth-8 training tree: 203 us with 8-cell
+    // pieces, 325 us with the frame's 32, 300 us in one pass)
+    if (n < PO_RAYS_SMALL) {
+        S.chunk_steps = PO_RAYS_CHUNK_STEPS;
+        S.chunk_cap = PO_RAYS_CHUNK_CAP;
+    }
     const int n_blocks = (int)((n + kBlock - 1) / kBlock);
     const int variant = po_fwd_variant(op, nullptr, t->kt);
     if (t->desc.dtype == PO_F32) {
@@ -1684,6 +1921,12 @@ hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, con
     } else {
         PO_DISPATCH_K(t->K, (split_t<__half, KK, 1>(t, job, n_blocks, variant, S, s)));
     }
+}
+
+hipError_t po_launch_backward_split(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
+                                    const float* rgb_fwd, const float* grad, float* gsig, float* gsh,
+                                    const KSplit& S, hipStream_t s) {
+    PO_DISPATCH_K(t->K, (backward_split_t<KK>(t, n, o, d, op, rgb_fwd, grad, gsig, gsh, S, s)));
 }
 
 hipError_t po_launch_backward(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,

@@ -275,8 +275,9 @@ def test_split_max_depth(po):
 
 @pytest.mark.parametrize("stop_T", [0.0, 1e-4])
 def test_split_ray_list(po, fog, stop_T):
-    # ray-list renders of >= 2^18 rays are split too; the viewer variant
-    # (aux outputs) walks them in one pass with the same colours
+    # ray-list renders of >= 65536 rays are split too (pieces of 8 cells
+    # below 2^18 rays, as in a camera render above); the viewer variant (aux
+    # outputs) walks them in one pass with the same colours
     import torch
 
     s, tree, ot = fog
@@ -297,8 +298,12 @@ def test_split_ray_list(po, fog, stop_T):
     _say(f"ray list: split vs one pass max {dd.max():.2e}, above 1e-5: {(dd > 1e-5).sum()}")
     assert np.mean(dd > 1e-5) <= 1e-4 and dd.max() <= stop_T + 1e-5
     # one ray fewer than the split size renders in one pass, bit-identical
-    small = po.render_rays(tree, og[:(1 << 18) - 1], dg[:(1 << 18) - 1], stop_T=stop_T).cpu().numpy()
-    assert np.array_equal(small, one[:(1 << 18) - 1])
+    small = po.render_rays(tree, og[:65535], dg[:65535], stop_T=stop_T).cpu().numpy()
+    assert np.array_equal(small, one[:65535])
+    # a list just above it is split with small pieces
+    mid = po.render_rays(tree, og[:70000], dg[:70000], stop_T=stop_T).cpu().numpy()
+    dm = np.abs(mid - one[:70000]).max(1)
+    assert np.mean(dm > 1e-5) <= 1e-4 and dm.max() <= stop_T + 1e-5
     rng = np.random.default_rng(31)
     idx = np.unique(np.concatenate([rng.choice(n, 2000, replace=False), np.argsort(-aux[:, 2])[:300]]))
     ref, _, _, _ = ot.render_rays(o[idx].astype(np.float64), d[idx].astype(np.float64), gamma=stop_T)
@@ -332,4 +337,66 @@ def test_split_codebook(po, fog):
     err = np.abs(img.reshape(-1, 3)[idx] - ref).max(1)
     _say(f"codebook: split vs oracle max {err.max():.2e}")
     assert err.max() <= TOL
+    assert po.device_errors() == 0
+
+
+def _cells_order(tree, gs, gsh):
+    perm = tree.perm
+    K = tree.K
+    a = np.zeros_like(gs)
+    b = np.zeros((len(perm), 3 * K), np.float64)
+    a[perm] = gs
+    b[perm] = gsh[:, :3 * K]
+    return a, b.reshape(-1, 3, K)
+
+
+@pytest.mark.parametrize("scene,gamma", [("fog", 1e-4), ("fog", 1e-2), ("blobs", 1e-4), ("blobs", 0.0)])
+def test_split_backward(po, fog, scene, gamma):
+    # backward passes of >= 65536 rays run in pieces: against the sum of two
+    # one-pass halves (float rounding apart) and the FP64 oracle gradient
+    import torch
+
+    if scene == "fog":
+        s, tree, ot = fog
+        o, d = scenes.random_rays(70000, 41, radius=2.5, spread=0.9)
+    else:
+        s = scenes.scene_blobs(depth=7, sh_degree=2, seed=8, data_seed=9)
+        tree = po.Tree.from_scene(s)
+        ot = oracle.OracleTree(s["depth"], s["sh_degree"], s["center"], s["half"], s["cells"], s["sigma"], s["sh"])
+        o, d = scenes.random_rays(70000, 43, radius=2.0, spread=0.8)
+    _say(f"split backward, {scene}, stop_T {gamma}")
+    g = np.random.default_rng(47).standard_normal((len(o), 3)).astype(np.float32)
+    bg = (0.9, 0.4, 0.1)
+    og, dg, gg = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (o, d, g))
+    rgb = po.render_rays(tree, og, dg, bg=bg, stop_T=gamma)
+    gs, gsh = po.render_rays_backward(tree, og, dg, rgb, gg, bg=bg, stop_T=gamma)
+    h = len(o) // 2
+    hs = torch.zeros_like(gs)
+    hsh = torch.zeros_like(gsh)
+    for a, b in ((0, h), (h, len(o))):
+        po.render_rays_backward(tree, og[a:b], dg[a:b], rgb[a:b], gg[a:b], bg=bg, stop_T=gamma, grad_sigma=hs,
+                                grad_sh=hsh)
+    torch.cuda.synchronize()
+    for got, ref, what in ((gs, hs, "dsigma"), (gsh, hsh, "dsh")):
+        got, ref = got.cpu().numpy().astype(np.float64), ref.cpu().numpy().astype(np.float64)
+        err = np.abs(got - ref)
+        scale = np.abs(ref).max()
+        _say(f"{scene} {gamma} {what}: split vs one pass max {err.max() / scale:.2e} of max|g|, "
+             f"entries above 1e-5: {(err > 1e-5 * scale).sum()}")
+        # where T lands within rounding of stop_T the two stop one cell apart:
+        # that cell's terms carry a factor T ~ stop_T
+        assert err.max() <= (2e-4 + gamma) * scale
+        assert np.mean(err > 1e-5 * scale) <= 1e-3
+    if gamma >= 1e-3:
+        # with 70000 rays some float32 transmittances land within rounding of
+        # a stop_T of 1e-2, where FP32 and FP64 stop one cell apart (both GPU
+        # paths alike, as compared above)
+        return
+    rs, rsh = ot.grad(o.astype(np.float64), d.astype(np.float64), g.astype(np.float64), bg=bg, gamma=gamma)
+    a, b = _cells_order(tree, gs.cpu().numpy().astype(np.float64), gsh.cpu().numpy().astype(np.float64))
+    for got, ref, what in ((a, rs, "dsigma"), (b, rsh, "dsh")):
+        scale = np.abs(ref).max()
+        err = np.abs(got - ref).max()
+        _say(f"{scene} {gamma} {what}: split vs oracle max {err / scale:.2e} of max|g|")
+        assert err <= 2e-4 * scale
     assert po.device_errors() == 0
