@@ -95,6 +95,7 @@ bool split_queue(void* stream, KSplit* S) {
     S->part2 = p + n * 48;
     S->split_steps = PO_SPLIT_STEPS;
     S->chunk_steps = PO_CHUNK_STEPS;
+    S->sub_steps = PO_SUB_STEPS;
     S->chunk_cap = PO_CHUNK_CAP;
     S->ub_frac = PO_SPLIT_UB_FRAC;
     S->ray_o = nullptr;

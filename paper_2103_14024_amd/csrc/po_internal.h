@@ -90,6 +90,9 @@ constexpr int kSplitMaxChunks = 16;
 #ifndef PO_CHUNK_STEPS
 #define PO_CHUNK_STEPS 32
 #endif
+#ifndef PO_SUB_STEPS
+#define PO_SUB_STEPS 12
+#endif
 #ifndef PO_CHUNK_CAP
 #define PO_CHUNK_CAP 24
 #endif
@@ -124,6 +127,7 @@ struct KSplit {
     void* part2;           // [kSplitSlots] 32-byte sub-chunk results
     int32_t split_steps;   // cells walked before a ray is handed on
     int32_t chunk_steps;   // target cells per chunk
+    int32_t sub_steps;     // target cells per sub-chunk
     int32_t chunk_cap;     // cells a chunk walks before its remainder is handed on
     float ub_frac;         // pieces cover at least this fraction of the finest-cell faces ahead
     const float* ray_o;    // ray-list renders: origins [n_rays][3] (camera renders: unused)

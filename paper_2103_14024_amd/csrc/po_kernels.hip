@@ -891,11 +891,12 @@ __device__ __forceinline__ void piece_bounds(const KJob& J, const KSplit& S, int
 // Pieces wanted for the rest [r.s, r.s_exit] of a walk that crossed `steps`
 // cells since s_first: about chunk_steps cells each, from the cells per unit
 // parameter so far, and at least ub_frac of the finest-cell faces ahead.
-__device__ __forceinline__ int pieces_wanted(const Ray& r, double s_first, int steps, const KSplit& S) {
+__device__ __forceinline__ int pieces_wanted(const Ray& r, double s_first, int steps, const KSplit& S,
+                                             int target) {
     const double rest = r.s_exit - r.s;
     double est = (double)steps * rest / fmax(r.s - s_first, 1e-300);
     est = fmax(est, (double)S.ub_frac * rest * (fabs(r.dg[0]) + fabs(r.dg[1]) + fabs(r.dg[2])));
-    return (int)fmin(fmax(ceil(est / (double)S.chunk_steps), 1.0), (double)kSplitMaxChunks);
+    return (int)fmin(fmax(ceil(est / (double)target), 1.0), (double)kSplitMaxChunks);
 }
 
 // Claims the wave's pieces in one atomic: sum(want) slots of a region, laid
@@ -963,7 +964,7 @@ __device__ __forceinline__ void first_walk(const KJob& J, const KSplit& S, int i
                 if (steps >= op.max_steps)
                     atomicAdd(&g_po_errors, 1ull);  // the step cap proper
                 else
-                    want = pieces_wanted(r, s_first, steps, S);
+                    want = pieces_wanted(r, s_first, steps, S, S.chunk_steps);
             }
         }
     }
@@ -1058,7 +1059,7 @@ __global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S)
                 if (steps >= J.op.max_steps) {
                     atomicAdd(&g_po_errors, 1ull);
                 } else {
-                    want = pieces_wanted(r, s_first, steps, S);
+                    want = pieces_wanted(r, s_first, steps, S, S.sub_steps);
 #ifdef PO_MIN_SUB
                     if (want < PO_MIN_SUB) {
                         march<Smp>(J.tr, r, J.op.max_steps - steps, stk, smp);
@@ -1415,7 +1416,7 @@ __global__ __launch_bounds__(kBlock) void k_backward_split(KBatch<1> B, KSplit S
             if (steps >= J.op.max_steps)
                 atomicAdd(&g_po_errors, 1ull);
             else
-                want = pieces_wanted(r, s_first, steps, S);
+                want = pieces_wanted(r, s_first, steps, S, S.chunk_steps);
         }
     }
     const int h = claim_pieces(S.count, S.info, (int)(blockIdx.x % kSplitRegions), want);
@@ -1812,6 +1813,7 @@ hipError_t backward_split_t(const po_tree* t, int64_t n, const float* o, const f
     // smaller pieces than the forward's: a backward step costs more (the
     // gradient atomics), and a batch of rays fills the chip less than a frame
     S.chunk_steps = PO_BWD_CHUNK_STEPS;
+    S.sub_steps = PO_BWD_CHUNK_STEPS;
     S.chunk_cap = PO_BWD_CHUNK_CAP;
 #define PO_BSPLIT(VEC_, NL_)                                                                                    \
     do {                                                                                                       \
@@ -1912,6 +1914,7 @@ hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, con
     // pieces, 325 us with the frame's 32, 300 us in one pass)
     if (n < PO_RAYS_SMALL) {
         S.chunk_steps = PO_RAYS_CHUNK_STEPS;
+        S.sub_steps = PO_RAYS_CHUNK_STEPS;
         S.chunk_cap = PO_RAYS_CHUNK_CAP;
     }
     const int n_blocks = (int)((n + kBlock - 1) / kBlock);
