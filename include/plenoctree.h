@@ -201,9 +201,10 @@ po_status po_tree_destroy(po_tree* t);
  * d_aux[n][4].  The colour is sum_i T_i (1 - exp(-sigma_i delta_i)) c_i +
  * T_N bg over the data segments met before the early stop (Sec. 3 eqn:quad,
  * App. B.3), c_i = sigmoid(sum_k sh[leaf][ch][k] Y_k(d)) (Sec. 4.1).
- * Lists of at least 65536 rays without viewer options are rendered in
- * pieces as po_render_camera describes (same queue, same equality up to
- * rounding).
+ * Lists of at least 65536 rays are rendered in pieces as po_render_camera
+ * describes (same queue, same equality up to rounding; with PO_OUT_AUX the
+ * sample and cell counts are summed over the pieces, a cell cut between two
+ * pieces counted once).
  * Errors: PO_ERR_INVALID (NULL tree/opts/arrays with n > 0, n < 0, bad
  * options), PO_ERR_DEVICE (launch failure). */
 po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, const float* d_dirs,
@@ -212,15 +213,14 @@ po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, co
 /* po_render_camera: renders a camera image into d_rgb[height][width][3]
  * (and d_aux[height][width][4] with PO_OUT_AUX).  width, height in
  * [1, 16384]; fx, fy non-zero.
- * Images of at least 65536 pixels without viewer options are rendered in
- * pieces: every ray is walked for a bounded number of cells, the rays with
+ * Images of at least 65536 pixels are rendered in pieces: every ray is walked for a bounded number of cells, the rays with
  * cells left are cut into parameter intervals walked in parallel, and the
  * pieces are composited front to back (compositing is associative, Sec. 3
  * eqn:quad), the piece holding the early stop walked again with the known
  * transmittance.  The colour equals the one-pass render (po_render_batch)
  * up to float rounding; where T lands within rounding of stop_T the two can
  * stop one cell apart, which moves at most stop_T of weight.  For this the
- * library keeps a work queue of about 300 MB per (device, stream), made on
+ * library keeps a work queue of about 400 MB per (device, stream), made on
  * the first such call and held until the process ends (if it cannot be
  * allocated, the image is rendered in one pass).  Calls on one stream are
  * ordered; calls on different streams use different queues.  Errors as for

@@ -89,10 +89,12 @@ bool split_queue(void* stream, KSplit* S) {
     S->info = reinterpret_cast<int4*>(p);
     S->head = p + n * 16;
     S->part = p + n * 48;
-    p += n * 80;
+    S->view_part = reinterpret_cast<int4*>(p + n * 80);
+    p += n * 96;
     S->info2 = reinterpret_cast<int4*>(p);
     S->head2 = p + n * 16;
     S->part2 = p + n * 48;
+    S->view_part2 = reinterpret_cast<int4*>(p + n * 80);
     S->split_steps = PO_SPLIT_STEPS;
     S->chunk_steps = PO_CHUNK_STEPS;
     S->sub_steps = PO_SUB_STEPS;
@@ -542,9 +544,9 @@ po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, co
     const int variant = po_fwd_variant(k, aux, t->kt);
     KSplit S;
     hipError_t e;
-    if ((variant == PO_FWD_SH || variant == PO_FWD_SG || variant == PO_FWD_CB) && n >= kSplitMinRays && n < (1ll << 31) &&
-        k.max_steps > PO_SPLIT_STEPS && split_queue(stream, &S))
-        e = po_launch_rays_split(t, n, d_origins, d_dirs, k, d_rgb, S, (hipStream_t)stream);
+    if (n >= kSplitMinRays && n < (1ll << 31) && k.max_steps > PO_SPLIT_STEPS && split_queue(stream, &S))
+        e = po_launch_rays_split(t, n, d_origins, d_dirs, k, d_rgb, variant == PO_FWD_VIEW ? aux : nullptr, S,
+                                 (hipStream_t)stream);
     else
         e = po_launch_rays(t, n, d_origins, d_dirs, k, d_rgb, aux, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "render_rays launch");
@@ -571,10 +573,9 @@ po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_rend
     j.block_begin = 0;
     j.tiles_x = (cam->width + PO_TILE - 1) / PO_TILE;
     const int variant = po_fwd_variant(j.op, j.aux, t->kt);
-    const bool plain = variant == PO_FWD_SH || variant == PO_FWD_SG || variant == PO_FWD_CB;
     KSplit S;
     hipError_t e;
-    if (plain && (int64_t)cam->width * cam->height >= kSplitMinPixels && j.op.max_steps > PO_SPLIT_STEPS &&
+    if ((int64_t)cam->width * cam->height >= kSplitMinPixels && j.op.max_steps > PO_SPLIT_STEPS &&
         split_queue(stream, &S))
         e = po_launch_camera_split(t, j, 4 * tiles_of(cam), variant, S, (hipStream_t)stream);
     else

@@ -125,6 +125,8 @@ struct KSplit {
     int4* info2;           // [kSplitSlots] the same for the sub-chunks of remainders
     void* head2;           // [kSplitSlots] 32-byte remainders, at their first slot
     void* part2;           // [kSplitSlots] 32-byte sub-chunk results
+    int4* view_part;       // [kSplitSlots] viewer variant: chunk samples, cells and cut flags
+    int4* view_part2;      // [kSplitSlots] the same for the sub-chunks
     int32_t split_steps;   // cells walked before a ray is handed on
     int32_t chunk_steps;   // target cells per chunk
     int32_t sub_steps;     // target cells per sub-chunk
@@ -135,7 +137,7 @@ struct KSplit {
     int64_t n_rays;
 };
 // Device bytes of the queues (counters, then info, head, part of each).
-constexpr size_t kSplitBytes = 512 + 2 * (size_t)kSplitSlots * (16 + 32 + 32);
+constexpr size_t kSplitBytes = 512 + 2 * (size_t)kSplitSlots * (16 + 32 + 32 + 16);
 
 struct po_tree {
     po_tree_desc desc;
@@ -164,15 +166,15 @@ hipError_t po_launch_backward(const po_tree* t, int64_t n, const float* o, const
 // workgroups, four per 16x16 tile.
 hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, int variant,
                                  hipStream_t s);
-// One camera job as the split render (plain SH, SG or codebook variants):
-// clears the queue counters and launches the four render kernels.
+// One camera job as the split render (any forward variant): clears the queue
+// counters and launches the four render kernels.
 // The queue must not be in use by work on another stream.
 hipError_t po_launch_camera_split(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
                                   hipStream_t s);
-// n rays (n < 2^31) of a plain SH, SG or codebook tree as the split render;
-// the queue must not be in use by work on another stream.
+// n rays (n < 2^31) as the split render (any forward variant; aux for the
+// viewer variant); the queue must not be in use by work on another stream.
 hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
-                                float* rgb, const KSplit& S, hipStream_t s);
+                                float* rgb, float* aux, const KSplit& S, hipStream_t s);
 // Backward of n rays (n < 2^31, float32 tree) in pieces: the first walk,
 // the forward of the pieces, their prefixes, then the backward of the pieces.
 hipError_t po_launch_backward_split(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,

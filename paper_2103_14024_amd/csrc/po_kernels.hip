@@ -582,20 +582,28 @@ struct CbSampler {
 // tested sample (-1: none); the chunk stops itself once T < stopT there,
 // since its walk cannot matter past that point for any transmittance in
 // front of it.
-template <class Base>
+template <class Base, bool COUNT = false>
 struct ChunkOf : Base {
     static constexpr bool kClip = true;
     static constexpr bool kChunk = true;
     bool cpl_next = true, cpl = true;
-    bool hit = false;  // stopped by stopT
+    bool hit = false;       // stopped by stopT
+    bool smp_cut = false;   // the last composited sample was cut by the walk's end
+    int issued = 0;         // issue() calls: the walk's first is its placeholder gather
+    int skip0 = 0;          // 1: the first cell had zero length (the walk began on its far face)
     float Tlast = -1.0f;
 
     __device__ __forceinline__ void issue(int leaf, float d, float t_in) {
         Base::issue(leaf, d, t_in);
         cpl = cpl_next;
+        if constexpr (COUNT) {
+            if (issued == 1) skip0 = d > 0.0f ? 0 : 1;
+            ++issued;
+        }
     }
     __device__ __forceinline__ bool consume() {
         const bool st = Base::consume();
+        if constexpr (COUNT) smp_cut = !cpl;
         if (!cpl) return false;
         Tlast = this->Tl;
         hit |= st;
@@ -605,9 +613,10 @@ struct ChunkOf : Base {
 
 // Samplers of the split render: the first walk's, and a piece's.
 template <typename T, int K, int VEC, int NL, int V>
-using FirstSampler = std::conditional_t<V == PO_FWD_CB, CbSampler<K, VEC, NL>, FwdSampler<T, K, VEC, NL, false>>;
+using FirstSampler = std::conditional_t<V == PO_FWD_CB, CbSampler<K, VEC, NL>,
+                                        FwdSampler<T, K, VEC, NL, V == PO_FWD_VIEW>>;
 template <typename T, int K, int VEC, int NL, int V>
-using ChunkSampler = ChunkOf<FirstSampler<T, K, VEC, NL, V>>;
+using ChunkSampler = ChunkOf<FirstSampler<T, K, VEC, NL, V>, V == PO_FWD_VIEW>;
 
 // Renders one ray: colour (background included), final T, samples, steps
 // and, in the viewer variant, the expected termination distance, SH subsets
@@ -821,10 +830,15 @@ static_assert(sizeof(SubHead) == 32, "queue record layout");
 // Result of a walked piece: colour and transmittance composited from T = 1,
 // T after its last tested sample (-1: none), and for a chunk its remainder's
 // sub-chunks (first slot, count; -1 none).
+// dep: the viewer variant's depth integral of the piece (from T = 1); its
+// samples and cells, and whether its last sample / cell was cut by the
+// piece's end (the next piece counts that cell again), go to a side record
+// {ns, steps, cut_smp, cut} that only the viewer variant touches.
 struct PieceOut {
     float c0, c1, c2, T;
     float Tlast;
-    int32_t sub, n_sub, pad;
+    int32_t sub, n_sub;
+    float dep;
 };
 static_assert(sizeof(PieceOut) == 32, "queue record layout");
 
@@ -840,11 +854,18 @@ __device__ __forceinline__ void fwd_init(Smp& smp, const KTree& tr, const KOpts&
         smp.cb_basis_bytes = (uint32_t)tr.cb_entries * 8u;
         smp.cb = raw_rsrc(tr.codebook, (uint32_t)K * smp.cb_basis_bytes);
     }
-    if constexpr (V == PO_FWD_SG)
+    if constexpr (V == PO_FWD_SG) {
         sg_basis<K>(tr.lobes, r.dn[0], r.dn[1], r.dn[2], smp.Y);
-    else
+    } else if constexpr (V == PO_FWD_VIEW) {
+        colour_basis<K>(tr, r.dn[0], r.dn[1], r.dn[2], smp.Y);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if ((op.sh_off >> k) & 1u) smp.Y[k] = 0.0f;
+    } else {
         sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], smp.Y);
+    }
 }
+
 
 // Ray idx of a split render: pixel idx = py * W + px of the job's camera
 // (SRC 0) or entry idx of the caller's ray arrays (SRC 1).
@@ -858,6 +879,21 @@ __device__ __forceinline__ void ray_of(const KJob& J, const KSplit& S, int idx, 
             ro[k] = (double)S.ray_o[3 * (size_t)idx + k];
             rd[k] = (double)S.ray_d[3 * (size_t)idx + k];
         }
+    }
+}
+
+// End parameter of a split ray's walk: the slicing plane of the viewer
+// variant, else 1e300 (the box exit).
+template <int V, int SRC>
+__device__ __forceinline__ double walk_end(const KJob& J, const KSplit& S, int idx) {
+    if constexpr (V == PO_FWD_VIEW) {
+        double ro[3], rd[3];
+        ray_of<SRC>(J, S, idx, ro, rd);
+        double lo, hi;
+        clip_range(J.op, ro, rd, lo, hi);
+        return hi;
+    } else {
+        return 1e300;
     }
 }
 
@@ -956,7 +992,9 @@ __device__ __forceinline__ void first_walk(const KJob& J, const KSplit& S, int i
     if (valid) {
         double ro[3], rd[3];
         ray_of<SRC>(J, S, idx, ro, rd);
-        if (ray_setup(tr, ro, rd, r)) {
+        double s_lo = 0.0, s_hi = 1e300;
+        if constexpr (V == PO_FWD_VIEW) clip_range(op, ro, rd, s_lo, s_hi);
+        if (ray_setup(tr, ro, rd, r, s_lo, s_hi)) {
             const double s_first = r.s;
             fwd_init<T, K, V>(smp, tr, op, r);
             steps = march<Smp, true>(tr, r, min(S.split_steps, op.max_steps), stk, smp);
@@ -983,14 +1021,24 @@ __device__ __forceinline__ void first_walk(const KJob& J, const KSplit& S, int i
             reinterpret_cast<ContHead*>(S.head)[h] = hd;
             handed = true;
         } else {
-            march<Smp>(tr, r, op.max_steps - steps, stk, smp);  // region full: finish here
+            steps += march<Smp>(tr, r, op.max_steps - steps, stk, smp);  // region full: finish here
         }
     }
+    const size_t p = (size_t)idx;
     if (valid && !handed) {
-        const size_t p = (size_t)idx;
         J.rgb[3 * p + 0] = fmaf(smp.Tl, op.bg[0], smp.c0);
         J.rgb[3 * p + 1] = fmaf(smp.Tl, op.bg[1], smp.c1);
         J.rgb[3 * p + 2] = fmaf(smp.Tl, op.bg[2], smp.c2);
+    }
+    if constexpr (V == PO_FWD_VIEW) {
+        // aux of a handed-on ray: the first walk's counts and depth, which
+        // the join completes
+        if (valid && J.aux) {
+            J.aux[4 * p + 0] = smp.Tl;
+            J.aux[4 * p + 1] = (float)smp.ns;
+            J.aux[4 * p + 2] = (float)steps;
+            J.aux[4 * p + 3] = smp.dep;
+        }
     }
 }
 
@@ -1051,7 +1099,7 @@ __global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S)
         const int mj = in.y;
         const ContHead hd = reinterpret_cast<const ContHead*>(S.head)[h];
         pix = hd.pix;
-        if (piece_setup<SRC>(J, S, pix, hd.s, 1e300, mj & 255, mj >> 8, r)) {
+        if (piece_setup<SRC>(J, S, pix, hd.s, walk_end<V, SRC>(J, S, pix), mj & 255, mj >> 8, r)) {
             const double s_first = r.s;
             fwd_init<T, K, V>(smp, J.tr, J.op, r);
             steps = march<Smp, true>(J.tr, r, min(S.chunk_cap, J.op.max_steps), stk, smp);
@@ -1080,7 +1128,7 @@ __global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S)
             sh.pad[0] = sh.pad[1] = sh.pad[2] = 0;
             reinterpret_cast<SubHead*>(S.head2)[sub] = sh;
         } else {
-            march<Smp>(J.tr, r, J.op.max_steps - steps, stk, smp);  // region full: finish here
+            steps += march<Smp>(J.tr, r, J.op.max_steps - steps, stk, smp);  // region full: finish here
             want = 0;
         }
     }
@@ -1093,8 +1141,11 @@ __global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S)
         o.Tlast = smp.Tlast;
         o.sub = sub;
         o.n_sub = want;
-        o.pad = 0;
+        o.dep = smp.dep;
         reinterpret_cast<PieceOut*>(S.part)[q] = o;
+        if constexpr (V == PO_FWD_VIEW)
+            S.view_part[q] = make_int4(smp.ns, steps - smp.skip0, smp.smp_cut ? 1 : 0,
+                                       (want == 0 && !smp.cpl) ? 1 : 0);
     }
 }
 
@@ -1111,10 +1162,11 @@ __global__ __launch_bounds__(kBlock) void k_render_subchunks(KBatch<1> B, KSplit
     using Smp = ChunkSampler<T, K, VEC, NL, V>;
     Smp smp;
     Ray r;
+    int steps = 0;
     if (piece_setup<SRC>(J, S, sh.pix, sh.lo, sh.hi, mj & 255, mj >> 8, r)) {
         fwd_init<T, K, V>(smp, J.tr, J.op, r);
         extern __shared__ int po_stack[];
-        march(J.tr, r, J.op.max_steps, po_stack + threadIdx.x, smp);
+        steps = march(J.tr, r, J.op.max_steps, po_stack + threadIdx.x, smp);
     }
     PieceOut o;
     o.c0 = smp.c0;
@@ -1124,42 +1176,69 @@ __global__ __launch_bounds__(kBlock) void k_render_subchunks(KBatch<1> B, KSplit
     o.Tlast = smp.Tlast;
     o.sub = -1;
     o.n_sub = 0;
-    o.pad = 0;
+    o.dep = smp.dep;
     reinterpret_cast<PieceOut*>(S.part2)[q] = o;
+    if constexpr (V == PO_FWD_VIEW)
+        S.view_part2[q] = make_int4(smp.ns, steps - smp.skip0, smp.smp_cut ? 1 : 0, smp.cpl ? 0 : 1);
 }
 
-// Front-to-back join of one piece with result o into (c, Tp): piece k of n
-// of [a, hi]; a chunk whose remainder was handed on (o.n_sub > 0) ends where
-// its remainder begins.  Returns true when early stopping ends the ray in
-// this piece.
+// Running state of a join: transmittance and colour in front, and for the
+// viewer variant the depth integral, sample and cell counts, and whether the
+// last piece joined ended in a cut cell (counted again by the next piece).
+struct JoinAcc {
+    float Tp;
+    float c[3];
+    float dep;
+    int ns, steps, cut_smp, cut;
+};
+
+// Front-to-back join of one piece with result o: piece k of n of [a, hi]; a
+// chunk whose remainder was handed on (o.n_sub > 0) ends where its remainder
+// begins.  Returns true when early stopping ends the ray in this piece.
 template <typename T, int K, int VEC, int NL, int V, int SRC>
 __device__ __forceinline__ bool join_piece(const KJob& J, const KSplit& S, int pix, double a, double hi, int k,
-                                           int n, const PieceOut& o, float& Tp, float (&c)[3]) {
-    if (o.Tlast >= 0.0f && Tp * o.Tlast < J.op.stop_T) {
+                                           int n, const PieceOut& o, const int4* vp, JoinAcc& A) {
+    if (o.Tlast >= 0.0f && A.Tp * o.Tlast < J.op.stop_T) {
         // the walk stops inside this piece: walk it again from Tp
         double lo, up;
         piece_bounds<SRC>(J, S, pix, a, hi, k, n, lo, up);
         if (o.n_sub > 0) up = reinterpret_cast<const SubHead*>(S.head2)[o.sub].lo;
         using Smp = ChunkSampler<T, K, VEC, NL, V>;
         Smp smp;
-        smp.Tl = Tp;
+        smp.Tl = A.Tp;
         Ray r;
+        int steps = 0;
         if (piece_setup<SRC>(J, S, pix, lo, up, 0, 1, r)) {
             fwd_init<T, K, V>(smp, J.tr, J.op, r);
             extern __shared__ int po_stack[];
-            march(J.tr, r, J.op.max_steps, po_stack + threadIdx.x, smp);
+            steps = march(J.tr, r, J.op.max_steps, po_stack + threadIdx.x, smp);
         }
-        c[0] += smp.c0;
-        c[1] += smp.c1;
-        c[2] += smp.c2;
-        Tp = smp.Tl;
+        A.c[0] += smp.c0;
+        A.c[1] += smp.c1;
+        A.c[2] += smp.c2;
+        A.Tp = smp.Tl;
+        if constexpr (V == PO_FWD_VIEW) {
+            A.dep += smp.dep;
+            A.cut_smp = smp.hit ? 0 : (smp.smp_cut ? 1 : 0);
+            A.cut = (smp.hit || o.n_sub > 0 || smp.cpl) ? 0 : 1;
+            A.ns += smp.ns - A.cut_smp;
+            A.steps += steps - smp.skip0 - A.cut;
+        }
         // (rounding can leave T just above stop_T; then the later pieces still count)
         return smp.hit;
     }
-    c[0] = fmaf(Tp, o.c0, c[0]);
-    c[1] = fmaf(Tp, o.c1, c[1]);
-    c[2] = fmaf(Tp, o.c2, c[2]);
-    Tp = Tp * o.T;
+    A.c[0] = fmaf(A.Tp, o.c0, A.c[0]);
+    A.c[1] = fmaf(A.Tp, o.c1, A.c[1]);
+    A.c[2] = fmaf(A.Tp, o.c2, A.c[2]);
+    if constexpr (V == PO_FWD_VIEW) {
+        const int4 c = *vp;  // ns, steps, cut_smp, cut
+        A.dep = fmaf(A.Tp, o.dep, A.dep);
+        A.ns += c.x - c.z;
+        A.steps += c.y - c.w;
+        A.cut_smp = c.z;
+        A.cut = c.w;
+    }
+    A.Tp = A.Tp * o.T;
     return false;
 }
 
@@ -1175,34 +1254,59 @@ __global__ __launch_bounds__(kBlock) void k_render_join(KBatch<1> B, KSplit S) {
     const PieceOut* part = reinterpret_cast<const PieceOut*>(S.part);
     const PieceOut* part2 = reinterpret_cast<const PieceOut*>(S.part2);
     const SubHead* head2 = reinterpret_cast<const SubHead*>(S.head2);
-    float Tp = hd.T;
-    float c[3] = {hd.c0, hd.c1, hd.c2};
+    const size_t p = (size_t)hd.pix;
+    JoinAcc A;
+    A.Tp = hd.T;
+    A.c[0] = hd.c0;
+    A.c[1] = hd.c1;
+    A.c[2] = hd.c2;
+    A.dep = 0.0f;
+    A.ns = A.steps = A.cut_smp = A.cut = 0;
+    if constexpr (V == PO_FWD_VIEW) {
+        if (J.aux) {
+            A.ns = (int)J.aux[4 * p + 1];
+            A.steps = (int)J.aux[4 * p + 2];
+            A.dep = J.aux[4 * p + 3];
+        }
+    }
+    const double end = walk_end<V, SRC>(J, S, hd.pix);
     bool done = false;
     int qj = q;
     for (int j = 0; j < m && !done; ++j) {
         const PieceOut o = part[qj];
+        const int qo = qj;
         qj = S.info[qj].z;
-        done = join_piece<T, K, VEC, NL, V, SRC>(J, S, hd.pix, hd.s, 1e300, j, m, o, Tp, c);
+        done = join_piece<T, K, VEC, NL, V, SRC>(J, S, hd.pix, hd.s, end, j, m, o, S.view_part + qo, A);
         if (o.n_sub > 0 && !done) {
             // the remainder's sub-chunks (bounds read only to walk one again)
             double slo = 0.0, shi = 0.0;
             int qk = o.sub;
             for (int k = 0; k < o.n_sub && !done; ++k) {
                 const PieceOut o2 = part2[qk];
+                const int qo2 = qk;
                 qk = S.info2[qk].z;
-                if (o2.Tlast >= 0.0f && Tp * o2.Tlast < J.op.stop_T && shi == 0.0) {
+                if (o2.Tlast >= 0.0f && A.Tp * o2.Tlast < J.op.stop_T && shi == 0.0) {
                     const SubHead sh = head2[o.sub];
                     slo = sh.lo;
                     shi = sh.hi;
                 }
-                done = join_piece<T, K, VEC, NL, V, SRC>(J, S, hd.pix, slo, shi, k, o.n_sub, o2, Tp, c);
+                done = join_piece<T, K, VEC, NL, V, SRC>(J, S, hd.pix, slo, shi, k, o.n_sub, o2, S.view_part2 + qo2,
+                                                         A);
             }
         }
     }
-    const size_t p = (size_t)hd.pix;
-    J.rgb[3 * p + 0] = fmaf(Tp, J.op.bg[0], c[0]);
-    J.rgb[3 * p + 1] = fmaf(Tp, J.op.bg[1], c[1]);
-    J.rgb[3 * p + 2] = fmaf(Tp, J.op.bg[2], c[2]);
+    J.rgb[3 * p + 0] = fmaf(A.Tp, J.op.bg[0], A.c[0]);
+    J.rgb[3 * p + 1] = fmaf(A.Tp, J.op.bg[1], A.c[1]);
+    J.rgb[3 * p + 2] = fmaf(A.Tp, J.op.bg[2], A.c[2]);
+    if constexpr (V == PO_FWD_VIEW) {
+        if (J.aux) {
+            // the last piece's cut cell (at the slicing plane) has no next piece
+            J.aux[4 * p + 0] = A.Tp;
+            J.aux[4 * p + 1] = (float)(A.ns + A.cut_smp);
+            J.aux[4 * p + 2] = (float)(A.steps + A.cut);
+            J.aux[4 * p + 3] = A.dep;
+        }
+    }
 }
 
 // Gradient of one ray's samples (App. B.3): the forward colour C is the
@@ -1450,7 +1554,20 @@ __device__ __forceinline__ void prefix_piece(const KJob& J, const KSplit& S, int
     w.T = Tp;
     w.Tlast = done ? -1.0f : 1.0f;
     *rec = w;
-    if (!done) done = join_piece<float, K, VEC, NL, V, 1>(J, S, pix, a, hi, k, n, o, Tp, P);
+    if (!done) {
+        JoinAcc A;
+        A.Tp = Tp;
+        A.c[0] = P[0];
+        A.c[1] = P[1];
+        A.c[2] = P[2];
+        A.dep = 0.0f;
+        A.ns = A.steps = A.cut_smp = A.cut = 0;
+        done = join_piece<float, K, VEC, NL, V, 1>(J, S, pix, a, hi, k, n, o, nullptr, A);
+        Tp = A.Tp;
+        P[0] = A.c[0];
+        P[1] = A.c[1];
+        P[2] = A.c[2];
+    }
 }
 
 template <int K, int VEC, int NL, int V>
@@ -1781,6 +1898,11 @@ hipError_t split_t(const po_tree* t, const KJob& job, int n_blocks, int variant,
             PO_SPLIT(P::FAST_VEC, P::FAST_NL, PO_FWD_SG);
         else
             PO_SPLIT(4, P::GEN_NL, PO_FWD_SG);
+    } else if (variant == PO_FWD_VIEW) {
+        if (fast)
+            PO_SPLIT(P::FAST_VEC, P::FAST_NL, PO_FWD_VIEW);
+        else
+            PO_SPLIT(4, P::GEN_NL, PO_FWD_VIEW);
     } else {
         if (fast)
             PO_SPLIT(P::FAST_VEC, P::FAST_NL, PO_FWD_SH);
@@ -1899,12 +2021,13 @@ hipError_t po_launch_camera_split(const po_tree* t, const KJob& job, int n_block
 }
 
 hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
-                                float* rgb, const KSplit& S0, hipStream_t s) {
+                                float* rgb, float* aux, const KSplit& S0, hipStream_t s) {
     KJob job;
     std::memset(&job, 0, sizeof job);
     job.tr = t->kt;
     job.op = op;
     job.rgb = rgb;
+    job.aux = aux;
     KSplit S = S0;
     S.ray_o = o;
     S.ray_d = d;
@@ -1918,7 +2041,7 @@ hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, con
         S.chunk_cap = PO_RAYS_CHUNK_CAP;
     }
     const int n_blocks = (int)((n + kBlock - 1) / kBlock);
-    const int variant = po_fwd_variant(op, nullptr, t->kt);
+    const int variant = po_fwd_variant(op, aux, t->kt);
     if (t->desc.dtype == PO_F32) {
         PO_DISPATCH_K(t->K, (split_t<float, KK, 1>(t, job, n_blocks, variant, S, s)));
     } else {

@@ -276,8 +276,8 @@ def test_split_max_depth(po):
 @pytest.mark.parametrize("stop_T", [0.0, 1e-4])
 def test_split_ray_list(po, fog, stop_T):
     # ray-list renders of >= 65536 rays are split too (pieces of 8 cells
-    # below 2^18 rays, as in a camera render above); the viewer variant (aux
-    # outputs) walks them in one pass with the same colours
+    # below 2^18 rays, as in a camera render above); the one-pass reference
+    # renders the list in runs of 65535 rays
     import torch
 
     s, tree, ot = fog
@@ -291,8 +291,10 @@ def test_split_ray_list(po, fog, stop_T):
     _say(f"split ray list, {n} rays, stop_T {stop_T}")
     og, dg = torch.from_numpy(o).cuda(), torch.from_numpy(d).cuda()
     rgb = po.render_rays(tree, og, dg, stop_T=stop_T).cpu().numpy()
-    one, aux = po.render_rays(tree, og, dg, stop_T=stop_T, aux=True)
-    one, aux = one.cpu().numpy(), aux.cpu().numpy()
+    runs = [po.render_rays(tree, og[a:a + 65535], dg[a:a + 65535], stop_T=stop_T, aux=True)
+            for a in range(0, n, 65535)]
+    one = np.concatenate([r[0].cpu().numpy() for r in runs])
+    aux = np.concatenate([r[1].cpu().numpy() for r in runs])
     assert (aux[:, 2] > 32).sum() > 60000
     dd = np.abs(rgb - one).max(1)
     _say(f"ray list: split vs one pass max {dd.max():.2e}, above 1e-5: {(dd > 1e-5).sum()}")
@@ -399,4 +401,55 @@ def test_split_backward(po, fog, scene, gamma):
         err = np.abs(got - ref).max()
         _say(f"{scene} {gamma} {what}: split vs oracle max {err / scale:.2e} of max|g|")
         assert err <= 2e-4 * scale
+    assert po.device_errors() == 0
+
+
+@pytest.mark.parametrize("kind", ["aux", "sh_off", "clip"])
+def test_split_view(po, fog, kind):
+    # the viewer variant through the split render: depth integral, samples
+    # and cells composed over the pieces, against the one-pass batch render
+    # and the oracle
+    import torch
+
+    s, tree, ot = fog
+    W = H = 256
+    cam, pose = _cam(po, W, H, seed=3)
+    off, plane = 0, None
+    if kind == "sh_off":
+        off = 0b0110
+    if kind == "clip":
+        plane = (0.3, -0.2, 0.9, 0.1)
+    _say(f"split viewer render: {kind}")
+    img, aux = po.render_camera(tree, cam, stop_T=1e-4, aux=True, sh_off=off, clip=plane)
+    img, aux = img.cpu().numpy().reshape(-1, 3), aux.cpu().numpy().reshape(-1, 4)
+    out = torch.empty((H, W, 3), device="cuda")
+    a1 = torch.empty((H, W, 4), device="cuda")
+    po.render_batch([po.Job(tree, cam, out, stop_T=1e-4, aux_out=a1, sh_off=off, clip=plane)])
+    torch.cuda.synchronize()
+    one, a1 = out.cpu().numpy().reshape(-1, 3), a1.cpu().numpy().reshape(-1, 4)
+    assert (a1[:, 2] > 32).sum() > 10000
+    d = np.abs(img - one).max(1)
+    _say(f"{kind}: rgb vs one pass max {d.max():.2e}; T {np.abs(aux[:, 0] - a1[:, 0]).max():.2e}; "
+         f"depth {np.abs(aux[:, 3] - a1[:, 3]).max():.2e}; samples equal {np.mean(aux[:, 1] == a1[:, 1]):.4f}; "
+         f"cells equal {np.mean(aux[:, 2] == a1[:, 2]):.4f}, max diff {np.abs(aux[:, 2] - a1[:, 2]).max():.0f}, "
+         f"mean split - one pass {np.mean(aux[:, 2] - a1[:, 2]):.3f}")
+    assert np.mean(d > 1e-5) <= 1e-4 and d.max() <= 1e-4 + 1e-5
+    assert np.abs(aux[:, 0] - a1[:, 0]).max() <= 1e-4 + 1e-5
+    assert np.abs(aux[:, 3] - a1[:, 3]).max() <= 1e-4 * (np.abs(a1[:, 3]).max() + 1.0)
+    # samples: a cell cut between two pieces counts once
+    assert np.mean(aux[:, 1] == a1[:, 1]) > 0.99 and np.abs(aux[:, 1] - a1[:, 1]).max() <= 2
+    # cells: a piece that starts on a face can visit the cell behind it for zero length
+    assert np.mean(aux[:, 2] == a1[:, 2]) > 0.9 and np.abs(aux[:, 2] - a1[:, 2]).max() <= 4
+    f32 = [float(np.float32(v)) for v in (cam.fx, cam.fy, cam.cx, cam.cy)]
+    o, dd = oracle.camera_rays(np.asarray(pose, np.float32).astype(np.float64), W, H, *f32)
+    rng = np.random.default_rng(53)
+    idx = np.unique(np.concatenate([rng.choice(W * H, 1500, replace=False), np.argsort(-a1[:, 2])[:200]]))
+    rr, T, ns, dep = ot.render_view(o[idx], dd[idx], gamma=1e-4, sh_off=off,
+                                    clip=None if plane is None else np.asarray(plane, np.float32))
+    _say(f"{kind}: vs oracle rgb {np.abs(img[idx] - rr).max():.2e} T {np.abs(aux[idx, 0] - T).max():.2e} "
+         f"depth {np.abs(aux[idx, 3] - dep).max():.2e}")
+    assert np.abs(img[idx] - rr).max() <= TOL
+    assert np.abs(aux[idx, 0] - T).max() <= TOL
+    assert np.all(np.abs(aux[idx, 3] - dep) <= TOL * (np.linalg.norm(o[idx], axis=1) + 2 * np.sqrt(3.0)))
+    assert np.mean(aux[idx, 1] == ns) > 0.99 and np.abs(aux[idx, 1] - ns).max() <= 2
     assert po.device_errors() == 0
