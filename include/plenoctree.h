@@ -282,8 +282,10 @@ po_status po_sgd_step(int64_t n, float* d_param, float* d_grad, float lr, int32_
  * image of one tree (tiles numbered row-major over ceil(W/16) x ceil(H/16)).
  * po_render_batch renders up to PO_BATCH_MAX_JOBS jobs, of any trees and
  * image sizes, with as few kernel launches as their (dtype, SH degree)
- * groups allow, all on `stream`.  Each job's pixels are computed exactly as
- * po_render_camera computes them.  Errors: as po_render_camera, plus
+ * groups allow, all on `stream`.  Each ray is walked to its end in one pass
+ * by one lane: a job's pixels equal po_render_camera's bit for bit for
+ * images under 65536 pixels, and up to float rounding for larger ones (which
+ * po_render_camera renders in pieces).  Errors: as po_render_camera, plus
  * PO_ERR_INVALID for n_jobs outside [0, PO_BATCH_MAX_JOBS] or a tile range
  * outside the image. */
 typedef struct {

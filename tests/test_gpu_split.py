@@ -1,11 +1,15 @@
-"""The split camera render against the one-pass render and the FP64 oracle.
+"""The split render and the split backward against the one-pass kernels and
+the FP64 oracle.
 
-Camera renders of 2^16 pixels or more walk every ray for a bounded number of
-cells, hand the rays with cells left on as chunks walked in parallel, and join
-the chunk results front to back (Sec. 3, eqn:quad: the composite of a range
-of segments acts on what lies behind it through its colour and
-transmittance).  Where early stopping ends a ray inside a chunk, the join
-walks that chunk again from the known transmittance.
+Camera renders of 2^16 pixels or more (and ray lists and backward passes of
+2^16 rays or more) walk every ray for a bounded number of cells, hand the
+rays with cells left on as pieces walked in parallel, and join the piece
+results front to back (Sec. 3, eqn:quad: the composite of a range of segments
+acts on what lies behind it through its colour and transmittance).  Where
+early stopping ends a ray inside a piece, the join walks that piece again
+from the known transmittance.  Covered: every compiled K, SG, float16 and
+codebook leaves, the viewer outputs, ray lists, the depth-15 tree, queue
+overflow, queue release and a second stream, and the gradients (App. B.3).
 
 The scene is a ball of fog: finest cells of moderate density, so that rays
 through its middle walk a hundred cells or more and reach T < 1e-4 deep inside
