@@ -37,14 +37,19 @@ STOP_T = 1e-4
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "render_camera_depth9_800x800_hbm_traffic.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2103_14024_amd", "csrc", "po_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2103_14024_amd", "csrc", f) for f in ("po_kernels.hip", "po_internal.h")]
 
 
 def kernel_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the kernel source and the
+    internal header that holds its tuning constants."""
     import hashlib
 
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for src in KERNEL_SRC:
+        with open(src, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def counter_traffic(dtype: str):

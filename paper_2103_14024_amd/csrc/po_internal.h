@@ -94,7 +94,7 @@ constexpr int kSplitMaxChunks = 16;
 #define PO_SUB_STEPS 12
 #endif
 #ifndef PO_CHUNK_CAP
-#define PO_CHUNK_CAP 24
+#define PO_CHUNK_CAP 32
 #endif
 #ifndef PO_SPLIT_UB_FRAC
 #define PO_SPLIT_UB_FRAC 0.2f
