@@ -26,6 +26,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -82,18 +84,28 @@ def record_bytes(tree) -> int:
     return es * (1 + 3 * tree.K)
 
 
+def timed_poses(steps: int, n: int = N_POSES) -> list:
+    """Pose of each timed frame: strided over all n poses (every pose once
+    when steps == n)."""
+    return [(i * n) // steps for i in range(steps)]
+
+
 def measure(po, tree, cams, steps, warmup, stream, aux_pass=True):
     import torch
 
     img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
-    # per-pose samples and traversal steps, outside the timed region
+    order = timed_poses(steps, len(cams))
+    poses = sorted(set(order))
+    # per-pose unit counts of the walk (samples, cells, child-entry reads) and
+    # lane efficiency, outside the timed region
     aux = torch.empty((H, W, po.AUX_WIDTH), dtype=torch.float32, device="cuda")
-    samples, tsteps, wave_iters = [], [], []
-    for cam in (cams if aux_pass else []):
-        po.render_camera(tree, cam, stop_T=STOP_T, aux=True, out=img, aux_out=aux, stream=stream)
+    stats, wave_iters = {}, []
+    for p in (poses if aux_pass else []):
+        stats[p] = po.traversal_stats(tree, cams[p], stop_T=STOP_T, stream=stream)
+        po.render_camera(tree, cams[p], stop_T=STOP_T, aux=True, out=img, aux_out=aux, stream=stream)
         a = aux.view(-1, po.AUX_WIDTH).sum(0).cpu()
-        samples.append(float(a[po.AUX_SAMPLES]))
-        tsteps.append(float(a[po.AUX_STEPS]))
+        # the aux output of the render counts the same samples and cells
+        assert int(a[po.AUX_SAMPLES]) == stats[p]["samples"] and int(a[po.AUX_STEPS]) == stats[p]["cells"], p
         # SIMD efficiency of the traversal loop: a wave (8x8 pixels) runs as
         # many iterations as its slowest lane
         st = aux[..., po.AUX_STEPS].view(H // 8, 8, W // 8, 8).amax(dim=(1, 3))
@@ -105,21 +117,27 @@ def measure(po, tree, cams, steps, warmup, stream, aux_pass=True):
     with torch.cuda.stream(stream):
         t0.record(stream)
         for i in range(steps):
-            po.render_camera(tree, cams[i % len(cams)], stop_T=STOP_T, out=img, stream=stream)
+            po.render_camera(tree, cams[order[i]], stop_T=STOP_T, out=img, stream=stream)
         t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
     rays = steps * W * H
     if not aux_pass:
-        return dict(ms=ms, ms_per_step=ms / steps, fps=steps / (ms * 1e-3), mrays_per_s=rays / (ms * 1e3))
-    n_samples = sum(samples[i % len(cams)] for i in range(steps))
-    n_steps = sum(tsteps[i % len(cams)] for i in range(steps))
-    lane_eff = sum(tsteps) / sum(wave_iters)
-    alg_bytes = n_samples * record_bytes(tree) + rays * 12
+        return dict(ms=ms, ms_per_step=ms / steps, fps=steps / (ms * 1e-3), mrays_per_s=rays / (ms * 1e3),
+                    poses_timed=len(poses))
+    n_samples = sum(stats[p]["samples"] for p in order)
+    n_cells = sum(stats[p]["cells"] for p in order)
+    n_loads = sum(stats[p]["node_loads"] for p in order)
+    lane_eff = sum(stats[p]["cells"] for p in poses) / sum(wave_iters)
+    rec = record_bytes(tree)
+    alg_bytes = n_samples * rec + n_loads * 4 + rays * 12
     return dict(ms=ms, ms_per_step=ms / steps, fps=steps / (ms * 1e-3), msamples_per_s=n_samples / (ms * 1e3),
-                mrays_per_s=rays / (ms * 1e3), samples_per_ray=n_samples / rays, steps_per_ray=n_steps / rays,
-                alg_gbps=alg_bytes / (ms * 1e-3) / 1e9, alg_bytes_per_launch=alg_bytes / steps,
-                lane_efficiency=lane_eff)
+                mrays_per_s=rays / (ms * 1e3), samples_per_ray=n_samples / rays, steps_per_ray=n_cells / rays,
+                node_loads_per_ray=n_loads / rays, alg_gbps=alg_bytes / (ms * 1e-3) / 1e9,
+                alg_bytes_per_launch=alg_bytes / steps,
+                alg_bytes_split={"records": n_samples * rec / steps, "child_entries": n_loads * 4 / steps,
+                                 "rays": rays * 12 / steps},
+                lane_efficiency=lane_eff, poses_timed=len(poses))
 
 
 def measure_one_pass(po, tree, cams, steps, warmup, stream):
@@ -128,7 +146,8 @@ def measure_one_pass(po, tree, cams, steps, warmup, stream):
     import torch
 
     img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
-    jobs = [[po.Job(tree, cam, img, stop_T=STOP_T)] for cam in cams]
+    jobs = [[po.Job(tree, cam, img, stop_T=STOP_T, one_pass=True)] for cam in cams]
+    order = timed_poses(steps, len(cams))
     for i in range(warmup):
         po.render_batch(jobs[i % len(cams)], stream=stream)
     torch.cuda.synchronize()
@@ -136,55 +155,99 @@ def measure_one_pass(po, tree, cams, steps, warmup, stream):
     with torch.cuda.stream(stream):
         t0.record(stream)
         for i in range(steps):
-            po.render_batch(jobs[i % len(cams)], stream=stream)
+            po.render_batch(jobs[order[i]], stream=stream)
         t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
     return {"fps": round(steps / (ms * 1e-3), 2), "ms_per_step": round(ms / steps, 4)}
 
 
-def cpu_baseline(scene, poses, budget_s=12.0):
-    """The FP64 oracle on the host cores, on a bounded sample of the same
-    workload (whole 800x800 frames of the first poses, then a random subset
-    of the next frame's pixels once the time budget is near); scaled to
-    frames per second."""
-    import numpy as np
+ERR_POSES = list(range(0, N_POSES, 20))   # poses whose frames the oracle renders (error and CPU baseline)
 
+
+def gpu_frames(po, tree, cams, poses):
+    """Host copies of the render_camera images of the given poses."""
+    out = {}
+    for p in poses:
+        out[p] = po.render_camera(tree, cams[p], stop_T=STOP_T).cpu().numpy()
+    return out
+
+
+def _err(a, b):
+    e = np.abs(np.asarray(a, np.float64) - np.asarray(b, np.float64)).reshape(-1, 3)
+    return {"max": [round(float(v), 8) for v in e.max(0)], "mean": [float("%.3e" % v) for v in e.mean(0)]}
+
+
+def cpu_baseline(scene, poses, frames32, frames16, budget_s=12.0, min_frames=5):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    workload: whole 800x800 frames of the poses in ERR_POSES (every 20th
+    pose), until ~budget_s of work and at least min_frames frames; scaled to
+    frames per second.  The same oracle frames give the per-channel error of
+    the GPU's float32 and float16 renders (frames32, frames16: host images of
+    those poses), and an oracle render of the float16-decoded tree on sampled
+    pixels gives the float16 form's parity on its own values."""
     import oracle
     from paper_2103_14024_amd import scenes
 
     t = oracle.OracleTree(scene["depth"], scene["sh_degree"], scene["center"], scene["half"], scene["cells"],
                           scene["sigma"], scene["sh"])
     fx, fy, cx, cy = scenes.intrinsics(W, H, 40.0)
-    rng = np.random.default_rng(0)
-    n, dt, frames = 0, 0.0, 0
-    for pose in poses:
-        o, d = oracle.camera_rays(pose, W, H, fx, fy, cx, cy)
-        if dt > 0 and dt * (1 + W * H / n) > budget_s:
-            m = int(max(1000, (budget_s - dt) / dt * n))
-            if m < W * H:
-                idx = rng.choice(W * H, m, replace=False)
-                o, d = o[idx], d[idx]
+    f32 = [float(np.float32(v)) for v in (fx, fy, cx, cy)]
+    n, dt, done = 0, 0.0, []
+    refs = {}
+    for p in ERR_POSES:
+        o, d = oracle.camera_rays(np.asarray(poses[p], np.float32).astype(np.float64), W, H, *f32)
         t0 = time.perf_counter()
-        t.render_rays(o, d, gamma=STOP_T)
+        rgb, _, _, _ = t.render_rays(o, d, gamma=STOP_T)
         dt += time.perf_counter() - t0
         n += len(o)
-        frames += 1
-        if dt >= budget_s:
+        done.append(p)
+        refs[p] = rgb.reshape(H, W, 3)
+        if dt >= budget_s and len(done) >= min_frames:
             break
     rays_per_s = n / dt
-    return {"value": rays_per_s / (W * H), "unit": "FPS", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{n} rays from {frames} of the 200 poses, 800x800, same scene ({dt:.1f} s of FP64 "
-                      f"rendering, {rays_per_s / 1e6:.2f} Mrays/s)"}
+    base = {"value": rays_per_s / (W * H), "unit": "FPS", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{len(done)} whole 800x800 frames (poses {done[0]}, {done[1]}, ... every 20th of the 200), "
+                      f"same scene, {dt:.1f} s of FP64 rendering, {rays_per_s / 1e6:.2f} Mrays/s"}
+    ref = np.stack([refs[p] for p in done])
+    err = {"poses": done, "pixels": int(ref.size // 3),
+           "f32_vs_oracle": _err(np.stack([frames32[p] for p in done]), ref)}
+    if frames16:
+        err["f16_vs_oracle_f32_values"] = _err(np.stack([frames16[p] for p in done]), ref)
+        # parity on the float16 values: the oracle on the decoded tree, 20000
+        # sampled pixels per frame
+        sig16 = np.asarray(scene["sigma"], np.float32).astype(np.float16).astype(np.float64)
+        sh16 = np.asarray(scene["sh"], np.float32).astype(np.float16).astype(np.float64)
+        t16 = oracle.OracleTree(scene["depth"], scene["sh_degree"], scene["center"], scene["half"], scene["cells"],
+                                sig16, sh16)
+        rng = np.random.default_rng(0)
+        got, want = [], []
+        for p in done:
+            idx = rng.choice(W * H, 20000, replace=False)
+            o, d = oracle.camera_rays(np.asarray(poses[p], np.float32).astype(np.float64), W, H, *f32)
+            want.append(t16.render_rays(o[idx], d[idx], gamma=STOP_T)[0])
+            got.append(frames16[p].reshape(-1, 3)[idx])
+        err["f16_vs_oracle_f16_values"] = dict(_err(np.concatenate(got), np.concatenate(want)),
+                                                pixels=int(sum(len(g) for g in got)))
+    return base, err
 
 
 def train_leg(po, scenes, steps=100, warmup=5, fit_steps=300, lr=1e7, batch=65536):
     """Differentiation workload: depth-8 blob tree (SH degree 2, float32),
     targets = 100 renders of 400x400 from the ground-truth tree, training
     from a copy perturbed by N(0, 0.3^2), SGD on random batches of 65536
-    rays.  Times full optimisation steps (forward, loss gradient, backward
-    with atomics, SGD) with HIP events and reports the dataset PSNR before
-    and after `fit_steps` steps."""
+    rays.  Times full optimisation steps (batch gather, forward, loss
+    gradient, backward with atomics, SGD) with HIP events and reports the
+    dataset PSNR before and after `fit_steps` steps.
+
+    Roofline of a step, algorithmic bytes: forward and backward each read
+    every sample's record (4 (1 + 3K) B) and every child entry of the walk
+    (4 B); the backward adds 1 + 3K float atomics per sample (a read and a
+    write of 4 B each); rays move 36 B in and 12 B out of the forward, 36 B
+    through the loss gradient, 48 B into the backward and 72 B through the
+    batch gather; SGD reads and writes the parameters and the gradients of
+    every leaf (16 B per value).  Samples and child-entry reads are counted
+    on the batches of the warm-up steps (outside the timed region)."""
     import torch
 
     gt = scenes.scene_train()
@@ -197,8 +260,13 @@ def train_leg(po, scenes, steps=100, warmup=5, fit_steps=300, lr=1e7, batch=6553
     tree = po.Tree.from_cells(gt["depth"], gt["sh_degree"], gt["cells"], sig, sh)
     m0 = po.optim.dataset_mse(tree, o, d, t)
     tr = po.Trainer(tree, o, d, t, lr_sigma=lr, lr_sh=lr, batch=batch, seed=1)
+    st = {"samples": 0, "node_loads": 0, "cells": 0}
+    warmup = max(1, warmup)
     for _ in range(warmup):
         tr.step()
+        c = po.traversal_stats(tree, origins=tr.bo, dirs=tr.bd, stop_T=tr.stop_T)
+        for k in st:
+            st[k] += c[k] / warmup
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -210,14 +278,28 @@ def train_leg(po, scenes, steps=100, warmup=5, fit_steps=300, lr=1e7, batch=6553
     for _ in range(max(0, fit_steps - steps - warmup)):
         tr.step()
     m1 = po.optim.dataset_mse(tree, o, d, t)
+    K = tree.K
+    rec = 4 * (1 + 3 * K)
+    walk = st["samples"] * rec + st["node_loads"] * 4
+    parts = {"forward": walk + batch * 48, "loss_grad": batch * 36,
+             "backward": walk + st["samples"] * (1 + 3 * K) * 8 + batch * 48, "batch_gather": batch * 72,
+             "sgd": tree.n_leaves * (1 + tree.stride) * 16}
+    alg = sum(parts.values())
+    gbps = alg / (ms * 1e-3) / 1e9
     return {"workload": "depth-8 blob band (%d leaves), SH degree 2, fp32, 100x400x400 targets, batch %d, "
                         "SGD lr %g" % (len(gt["cells"]), batch, lr),
             "ms_per_step": round(ms, 4), "mrays_per_s": round(batch / ms / 1e3, 2),
+            "samples_per_ray": round(st["samples"] / batch, 3), "cells_per_ray": round(st["cells"] / batch, 2),
+            "child_entry_reads_per_ray": round(st["node_loads"] / batch, 2),
+            "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": round(gbps / HBM_PEAK_GBPS, 4), "alg_bytes_per_step": int(alg),
+                         "alg_bytes_per_step_parts": {k: int(v) for k, v in parts.items()},
+                         "atomics_per_step": int(st["samples"] * (1 + 3 * K))},
             "psnr_start": round(po.psnr(m0), 2), "psnr_after": round(po.psnr(m1), 2), "steps_fitted": fit_steps,
             "paper_context": "about 3M rays/s on a Tesla V100 (NeRF-synthetic)"}
 
 
-def serve_leg(po, scenes, rates=(50, 100, 200, 350, 500), n_requests=300, budget_mb=1024):
+def serve_leg(po, scenes, rates=(50, 100, 200, 350, 500, 1000, 1500, 2000), n_requests=2000, budget_mb=1024):
     """Serving workload: four float16 scenes resident in HBM (depth 8/9/9/10,
     SH degree 2/3/2/3), Poisson arrivals at each rate, resolutions uniform
     over 256^2, 512^2, 800^2, 1280x720 and 1920x1080, random upper-hemisphere
@@ -397,10 +479,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=300, help="requests per arrival rate")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--no-extra", action="store_true", help="skip the viewer, filter and basis-sweep legs")
     ap.add_argument("--profile", action="store_true",
                     help="time the float32 renders only (no sample-count pass, fp16 or CPU legs); no JSON line")
+    ap.add_argument("--train-only", action="store_true",
+                    help="run the differentiation leg alone and print its JSON (for profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -419,6 +503,9 @@ def main():
     torch.cuda.set_device(0)
     if args.calib_copy_mib:
         calib_copy(args.calib_copy_mib)
+    if args.train_only:
+        print(json.dumps(train_leg(po, scenes, steps=args.steps, warmup=args.warmup, fit_steps=0)), flush=True)
+        return
     t0 = time.perf_counter()
     scene = scenes.scene_blobs()
     log(f"scene: {len(scene['cells'])} leaves in {time.perf_counter() - t0:.1f} s")
@@ -437,7 +524,8 @@ def main():
     r32 = measure(po, tree32, cams, args.steps, args.warmup, stream)
     log(f"fp32: {r32['fps']:.1f} FPS, {r32['msamples_per_s']:.0f} Msamples/s, "
         f"{r32['samples_per_ray']:.2f} samples/ray, {r32['steps_per_ray']:.1f} steps/ray, "
-        f"lane efficiency {r32['lane_efficiency']:.3f}")
+        f"{r32['node_loads_per_ray']:.1f} child-entry reads/ray, lane efficiency {r32['lane_efficiency']:.3f}")
+    frames32 = {} if args.no_cpu_baseline else gpu_frames(po, tree32, cams, ERR_POSES)
     one32 = measure_one_pass(po, tree32, cams, args.steps, args.warmup, stream)
     log(f"fp32 one pass: {one32['fps']:.1f} FPS")
     tb = counter_traffic("f32")
@@ -448,9 +536,11 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "plenoctree-render depth-9 blob band, SH degree 3, 800x800, 200 hemisphere poses",
                    "leaves": int(len(scene["cells"])), "nodes": int(tree32.n_nodes), "depth": 9, "sh_degree": 3,
-                   "width": W, "height": H, "poses": N_POSES, "stop_T": STOP_T, "leaf_dtype": "f32"},
+                   "width": W, "height": H, "poses": N_POSES, "poses_timed": r32["poses_timed"],
+                   "stop_T": STOP_T, "leaf_dtype": "f32"},
         "msamples_per_s": round(r32["msamples_per_s"], 1), "mrays_per_s": round(r32["mrays_per_s"], 1),
         "samples_per_ray": round(r32["samples_per_ray"], 3), "steps_per_ray": round(r32["steps_per_ray"], 2),
+        "child_entry_reads_per_ray": round(r32["node_loads_per_ray"], 2),
         "lane_efficiency": round(r32["lane_efficiency"], 4),
         "one_pass": one32,
         "roofline": {"bound": "hbm", "achieved": round(r32["alg_gbps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -458,6 +548,7 @@ def main():
                      "kernel": "render pass <float,16,16,48,SH>: k_zero_i32, k_render_camera_split, "
                                "k_render_chunks, k_render_subchunks, k_render_join",
                      "alg_bytes_per_frame": int(r32["alg_bytes_per_launch"]),
+                     "alg_bytes_per_frame_parts": {k: int(v) for k, v in r32["alg_bytes_split"].items()},
                      "hbm_bytes_per_frame": None if tb is None else int(tb)},
         "paper_context": {"fps": 167.68, "hardware": "Tesla V100", "workload": "NeRF-synthetic real scenes"},
     }
@@ -468,15 +559,19 @@ def main():
         log(f"filter: {out['filter']}")
     del tree32
     torch.cuda.empty_cache()
+    frames16 = {}
     if not args.no_fp16:
         tree16 = po.Tree.from_scene(scene, dtype="f16")
         r16 = measure(po, tree16, cams, args.steps, args.warmup, stream)
         log(f"fp16: {r16['fps']:.1f} FPS, {r16['msamples_per_s']:.0f} Msamples/s")
         one16 = measure_one_pass(po, tree16, cams, args.steps, args.warmup, stream)
+        if not args.no_cpu_baseline:
+            frames16 = gpu_frames(po, tree16, cams, ERR_POSES)
         t16 = counter_traffic("f16")
         out["fp16"] = {"fps": round(r16["fps"], 2), "ms_per_step": round(r16["ms_per_step"], 4),
                        "msamples_per_s": round(r16["msamples_per_s"], 1),
                        "alg_gbps": round(r16["alg_gbps"], 1), "alg_frac": round(r16["alg_gbps"] / HBM_PEAK_GBPS, 4),
+                       "alg_bytes_per_frame": int(r16["alg_bytes_per_launch"]),
                        "hbm_gbps": None if t16 is None else round(t16 / (r16["ms_per_step"] * 1e-3) / 1e9, 1),
                        "speedup_vs_fp32": round(r16["fps"] / r32["fps"], 3), "one_pass": one16}
         del tree16
@@ -492,8 +587,16 @@ def main():
     if not args.no_serve:
         out["serve"] = serve_leg(po, scenes, n_requests=args.serve_requests)
     if not args.no_cpu_baseline:
-        log("cpu baseline (FP64 oracle)")
-        out["cpu_baseline"] = cpu_baseline(scene, poses)
+        log("cpu baseline (FP64 oracle) and the error of the GPU renders against it")
+        out["cpu_baseline"], err = cpu_baseline(scene, poses, frames32, frames16)
+        out["error_vs_fp64_oracle"] = {"poses": err["poses"], "pixels": err["pixels"],
+                                       "f32": err["f32_vs_oracle"]}
+        if "fp16" in out and "f16_vs_oracle_f32_values" in err:
+            out["fp16"]["error_vs_fp64_oracle"] = {
+                "poses": err["poses"], "pixels": err["pixels"],
+                "vs_float32_values": err["f16_vs_oracle_f32_values"],
+                "vs_float16_values": err["f16_vs_oracle_f16_values"]}
+        log(f"error vs oracle: {err}")
     print(json.dumps(out), flush=True)
 
 

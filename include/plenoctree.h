@@ -109,11 +109,15 @@ typedef struct {
  * rejects them.  A call that sets none of them and no PO_OUT_AUX runs the
  * plain kernels. */
 #define PO_OUT_AUX 1u
+/* PO_ONE_PASS: walk every ray to its end in one pass by one lane, also where
+ * po_render_camera, po_render_rays or po_render_batch would render in pieces
+ * (the reference of the split render's equality, and for timing it). */
+#define PO_ONE_PASS 2u
 typedef struct {
     float bg[3];        /* background colour c_N (App. B.3) */
     float stop_T;       /* early stop once T < stop_T after a data segment (Sec. 4.2); 0 disables */
     int32_t max_steps;  /* cap on traversal steps per ray; 0 = 3*2^D + 8, which valid trees never reach */
-    uint32_t flags;     /* PO_OUT_* */
+    uint32_t flags;     /* PO_OUT_AUX | PO_ONE_PASS */
     uint32_t sh_off;    /* SH basis functions left out (bit k = function k); 0 = none */
     float clip[4];      /* slicing half-space n.x + w >= 0; all zero = none */
 } po_render_opts;
@@ -281,13 +285,17 @@ po_status po_sgd_step(int64_t n, float* d_param, float* d_grad, float lr, int32_
  * One job renders the 16x16 tiles [tile_begin, tile_end) of one camera
  * image of one tree (tiles numbered row-major over ceil(W/16) x ceil(H/16)).
  * po_render_batch renders up to PO_BATCH_MAX_JOBS jobs, of any trees and
- * image sizes, with as few kernel launches as their (dtype, SH degree)
- * groups allow, all on `stream`.  Each ray is walked to its end in one pass
- * by one lane: a job's pixels equal po_render_camera's bit for bit for
- * images under 65536 pixels, and up to float rounding for larger ones (which
- * po_render_camera renders in pieces).  Errors: as po_render_camera, plus
- * PO_ERR_INVALID for n_jobs outside [0, PO_BATCH_MAX_JOBS] or a tile range
- * outside the image. */
+ * image sizes, all on `stream`.  Jobs of fewer than 256 tiles (65536 pixels)
+ * are rendered with as few kernel launches as their (dtype, SH degree)
+ * groups allow, each ray walked to its end in one pass by one lane; their
+ * pixels equal po_render_camera's bit for bit for images under 65536
+ * pixels.  A job of 256 tiles or more (without PO_ONE_PASS in its options)
+ * is rendered in pieces on its own, as
+ * po_render_camera renders a large image (using the same work queue of
+ * `stream`), and its pixels equal po_render_camera's up to float rounding
+ * (bit for bit unless a region of the work queue filled up in one of the
+ * two).  Errors: as po_render_camera, plus PO_ERR_INVALID for n_jobs outside
+ * [0, PO_BATCH_MAX_JOBS] or a tile range outside the image. */
 typedef struct {
     const po_tree* tree;
     po_camera cam;
@@ -354,13 +362,42 @@ po_status po_leaf_weights(const po_tree* t, const po_camera* cam, const po_rende
 po_status po_tree_leaf_cells(const po_tree_desc* desc, int64_t n_nodes, const int32_t* h_child, int64_t n_leaves,
                              int32_t* h_cells);
 
+/* -------------------------------------------------------------- statistics
+ * po_traversal_stats: walks every pixel-centre ray of a camera through the
+ * tree once, as the one-pass render does (Sec. 4.2, "Rendering": the exact
+ * segments between voxel boundaries, early stop on the transmittance), and
+ * writes h_stats[4] = {rays, data samples, cells visited, child entries read}
+ * summed over the image: a data sample is a segment of positive length in a
+ * data leaf before the early stop (the samples column of the aux output),
+ * cells are the steps of the walk, and child entries are the 4-byte node
+ * reads of its descents (each descent restarts below the deepest ancestor
+ * shared with the previous cell).  These are the per-frame unit counts of the
+ * render's algorithmic bytes.  Only densities are gathered; bg and colours
+ * play no part.  Synchronous: waits for `stream`; concurrent calls are
+ * serialised.  opts must not set flags, sh_off or a slicing plane.  Errors:
+ * PO_ERR_INVALID, PO_ERR_UNSUPPORTED (viewer options), PO_ERR_DEVICE. */
+po_status po_traversal_stats(const po_tree* t, const po_camera* cam, const po_render_opts* opts, int64_t* h_stats,
+                             void* stream);
+/* po_traversal_stats_rays: the same for the n rays (d_origins, d_dirs) as
+ * po_render_rays takes them, each walked to its end in one pass; n == 0
+ * writes zeros. */
+po_status po_traversal_stats_rays(const po_tree* t, int64_t n, const float* d_origins, const float* d_dirs,
+                                  const po_render_opts* opts, int64_t* h_stats, void* stream);
+
 /* --------------------------------------------------------------- resources
+ * po_reserve_queues: allocates now the work queue that split renders,
+ * split ray lists and split backward passes on `stream` use (about 400 MB on
+ * the current device, held until po_release_queues or the end of the
+ * process), so that the first such call on the stream allocates nothing.
+ * Does nothing if the queue exists.  Errors: PO_ERR_DEVICE (allocation
+ * failed; later calls then render in one pass).
  * po_release_queues: frees the work queues of the split render (one per
  * device and stream that rendered in pieces; see po_render_camera) after
  * waiting for all work on each of their devices.  Later split renders make
  * new ones.  Call it from one thread while no render is being issued.
  * Errors: PO_ERR_DEVICE (a wait or free failed; the remaining queues are
  * still released). */
+po_status po_reserve_queues(void* stream);
 po_status po_release_queues(void);
 
 /* ----------------------------------------------------------------- errors

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(PKG, "libplenoctree.so")
 PO_OK, PO_ERR_INVALID, PO_ERR_TREE, PO_ERR_OOM, PO_ERR_DEVICE, PO_ERR_UNSUPPORTED = range(6)
 PO_F32, PO_F16 = 0, 1
 PO_OUT_AUX = 1
+PO_ONE_PASS = 2
 PO_WEIGHT_ALPHA, PO_WEIGHT_CONTRIB = 0, 1
 PO_MAX_DEPTH = 15
 PO_MAX_SH_DEGREE = 4
@@ -79,6 +80,9 @@ _SIGS = {
     "po_device_errors": [ctypes.POINTER(_I64)],
     "po_device_errors_reset": [],
     "po_release_queues": [],
+    "po_reserve_queues": [_P],
+    "po_traversal_stats": [_P, ctypes.POINTER(po_camera), ctypes.POINTER(po_render_opts), _P, _P],
+    "po_traversal_stats_rays": [_P, _I64, _P, _P, ctypes.POINTER(po_render_opts), _P, _P],
 }
 EXPORTS = list(_SIGS) + ["po_status_str", "po_last_error", "po_version"]
 

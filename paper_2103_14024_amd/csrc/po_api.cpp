@@ -74,15 +74,24 @@ bool split_queue(void* stream, KSplit* S) {
         if (it != g_split.end()) {
             base = it->second;
         } else {
-            if (hipMalloc(&base, kSplitBytes) != hipSuccess) {
+            if (hipMalloc(&base, po_split_bytes(kSplitRegionSlots)) != hipSuccess) {
                 (void)hipGetLastError();
                 return false;
             }
             g_split[{dev, stream}] = base;
         }
     }
+    po_split_layout(base, kSplitRegionSlots, S);
+    return true;
+}
+
+}  // namespace
+
+po_status po_report(po_status s, const char* msg) { return s == PO_OK ? ok() : fail(s, "%s", msg); }
+
+void po_split_layout(void* base, int region_slots, KSplit* S) {
     char* p = static_cast<char*>(base);
-    const size_t n = (size_t)kSplitSlots;
+    const size_t n = (size_t)kSplitRegions * (size_t)region_slots;
     S->count = reinterpret_cast<int32_t*>(p);
     S->count2 = S->count + kSplitRegions;
     p += 512;
@@ -95,6 +104,7 @@ bool split_queue(void* stream, KSplit* S) {
     S->head2 = p + n * 16;
     S->part2 = p + n * 48;
     S->view_part2 = reinterpret_cast<int4*>(p + n * 80);
+    S->region_slots = region_slots;
     S->split_steps = PO_SPLIT_STEPS;
     S->chunk_steps = PO_CHUNK_STEPS;
     S->sub_steps = PO_SUB_STEPS;
@@ -103,12 +113,7 @@ bool split_queue(void* stream, KSplit* S) {
     S->ray_o = nullptr;
     S->ray_d = nullptr;
     S->n_rays = 0;
-    return true;
 }
-
-}  // namespace
-
-po_status po_report(po_status s, const char* msg) { return s == PO_OK ? ok() : fail(s, "%s", msg); }
 
 namespace {
 
@@ -149,7 +154,7 @@ po_status check_opts(const po_render_opts* o) {
         if (!finite(o->bg[k])) return fail(PO_ERR_INVALID, "background must be finite");
     if (!(o->stop_T >= 0.0f) || !finite(o->stop_T)) return fail(PO_ERR_INVALID, "stop_T must be finite and >= 0");
     if (o->max_steps < 0) return fail(PO_ERR_INVALID, "max_steps must be >= 0");
-    if (o->flags & ~PO_OUT_AUX) return fail(PO_ERR_INVALID, "unknown flags 0x%x", o->flags);
+    if (o->flags & ~(PO_OUT_AUX | PO_ONE_PASS)) return fail(PO_ERR_INVALID, "unknown flags 0x%x", o->flags);
     for (int k = 0; k < 4; ++k)
         if (!finite(o->clip[k])) return fail(PO_ERR_INVALID, "slicing plane must be finite");
     return PO_OK;
@@ -544,7 +549,8 @@ po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, co
     const int variant = po_fwd_variant(k, aux, t->kt);
     KSplit S;
     hipError_t e;
-    if (n >= kSplitMinRays && n < (1ll << 31) && k.max_steps > PO_SPLIT_STEPS && split_queue(stream, &S))
+    if (!(k.flags & PO_ONE_PASS) && n >= kSplitMinRays && n < (1ll << 31) && k.max_steps > PO_SPLIT_STEPS &&
+        split_queue(stream, &S))
         e = po_launch_rays_split(t, n, d_origins, d_dirs, k, d_rgb, variant == PO_FWD_VIEW ? aux : nullptr, S,
                                  (hipStream_t)stream);
     else
@@ -575,8 +581,8 @@ po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_rend
     const int variant = po_fwd_variant(j.op, j.aux, t->kt);
     KSplit S;
     hipError_t e;
-    if ((int64_t)cam->width * cam->height >= kSplitMinPixels && j.op.max_steps > PO_SPLIT_STEPS &&
-        split_queue(stream, &S))
+    if (!(j.op.flags & PO_ONE_PASS) && (int64_t)cam->width * cam->height >= kSplitMinPixels &&
+        j.op.max_steps > PO_SPLIT_STEPS && split_queue(stream, &S))
         e = po_launch_camera_split(t, j, 4 * tiles_of(cam), variant, S, (hipStream_t)stream);
     else
         e = po_launch_camera_jobs(t, 1, &j, 4 * tiles_of(cam), variant, (hipStream_t)stream);
@@ -600,7 +606,8 @@ po_status po_render_rays_backward(const po_tree* t, int64_t n, const float* d_or
     const KOpts k = kopts(t, opts);
     KSplit S;
     hipError_t e;
-    if (n >= kSplitMinBackward && n < (1ll << 31) && k.max_steps > PO_SPLIT_STEPS && split_queue(stream, &S))
+    if (!(k.flags & PO_ONE_PASS) && n >= kSplitMinBackward && n < (1ll << 31) && k.max_steps > PO_SPLIT_STEPS &&
+        split_queue(stream, &S))
         e = po_launch_backward_split(t, n, d_origins, d_dirs, k, d_rgb_fwd, d_grad_rgb, d_grad_sigma, d_grad_sh, S,
                                      (hipStream_t)stream);
     else
@@ -671,6 +678,30 @@ po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream) {
         return 4 * po_plan_id(J.tree) + po_fwd_variant(kopts(J.tree, &J.opts), aux, J.tree->kt);
     };
     bool done[PO_BATCH_MAX_JOBS] = {false};
+    // jobs of at least kSplitMinPixels pixels (whole tiles) are rendered in
+    // pieces, each on its own, as po_render_camera renders a large image
+    for (int i = 0; i < n_jobs; ++i) {
+        const po_job& J = jobs[i];
+        const int nt = J.tile_end - J.tile_begin;
+        const KOpts k = kopts(J.tree, &J.opts);
+        KSplit S;
+        if ((k.flags & PO_ONE_PASS) || (int64_t)nt * PO_TILE * PO_TILE < kSplitMinPixels ||
+            k.max_steps <= PO_SPLIT_STEPS || !split_queue(stream, &S))
+            continue;
+        done[i] = true;
+        KJob kj;
+        std::memset(&kj, 0, sizeof kj);
+        kj.tr = J.tree->kt;
+        kj.cam = kcam(&J.cam);
+        kj.op = k;
+        kj.rgb = J.d_rgb;
+        kj.aux = (J.opts.flags & PO_OUT_AUX) ? J.d_aux : nullptr;
+        kj.tile_begin = J.tile_begin;
+        kj.block_begin = 0;
+        kj.tiles_x = (J.cam.width + PO_TILE - 1) / PO_TILE;
+        hipError_t e = po_launch_camera_split(J.tree, kj, 4 * nt, variant(i) % 4, S, (hipStream_t)stream);
+        if (e != hipSuccess) return device_fail(e, "render_batch launch");
+    }
     for (int i = 0; i < n_jobs; ++i) {
         if (done[i]) continue;
         const int plan = variant(i);
@@ -714,6 +745,53 @@ po_status po_leaf_weights(const po_tree* t, const po_camera* cam, const po_rende
     if (!d_weight && t->n_leaves > 0) return fail(PO_ERR_INVALID, "weight array is NULL");
     hipError_t e = po_launch_leaf_weights(t, kcam(cam), k, mode, d_weight, d_alpha, (hipStream_t)stream);
     if (e != hipSuccess) return device_fail(e, "leaf_weights launch");
+    return ok();
+}
+
+namespace {
+po_status traversal_stats(const po_tree* t, const po_camera* cam, int64_t n, const float* d_o, const float* d_d,
+                          const po_render_opts* opts, int64_t* h_stats, void* stream) {
+    if (!h_stats) return fail(PO_ERR_INVALID, "stats array is NULL");
+    if (opts->flags != 0) return fail(PO_ERR_INVALID, "statistics take no output flags");
+    const KOpts k = kopts(t, opts);
+    if (po_view_opts(k, nullptr)) return fail(PO_ERR_UNSUPPORTED, "statistics take no sh_off or slicing plane");
+    unsigned long long v[4] = {0, 0, 0, 0};
+    hipError_t e = hipSuccess;
+    if (cam || n > 0) {
+        static std::mutex mu;
+        std::lock_guard<std::mutex> lk(mu);
+        KCam kc;
+        if (cam) kc = kcam(cam);
+        e = po_traversal_stats_sync(t, cam ? &kc : nullptr, n, d_o, d_d, k, v, (hipStream_t)stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "traversal_stats");
+    for (int i = 0; i < 4; ++i) h_stats[i] = (int64_t)v[i];
+    return ok();
+}
+}  // namespace
+
+po_status po_traversal_stats(const po_tree* t, const po_camera* cam, const po_render_opts* opts, int64_t* h_stats,
+                             void* stream) {
+    if (!t) return fail(PO_ERR_INVALID, "tree is NULL");
+    if (po_status s = check_camera(cam)) return s;
+    if (po_status s = check_opts(opts)) return s;
+    return traversal_stats(t, cam, 0, nullptr, nullptr, opts, h_stats, stream);
+}
+
+po_status po_traversal_stats_rays(const po_tree* t, int64_t n, const float* d_origins, const float* d_dirs,
+                                  const po_render_opts* opts, int64_t* h_stats, void* stream) {
+    if (!t) return fail(PO_ERR_INVALID, "tree is NULL");
+    if (po_status s = check_opts(opts)) return s;
+    if (n < 0 || n >= (1ll << 37)) return fail(PO_ERR_INVALID, "n = %lld out of range", (long long)n);
+    if (n > 0 && (!d_origins || !d_dirs)) return fail(PO_ERR_INVALID, "ray array is NULL");
+    return traversal_stats(t, nullptr, n, d_origins, d_dirs, opts, h_stats, stream);
+}
+
+po_status po_reserve_queues(void* stream) {
+    KSplit S;
+    if (!split_queue(stream, &S))
+        return fail(PO_ERR_DEVICE, "could not allocate the split-render work queue (%zu bytes)",
+                    po_split_bytes(kSplitRegionSlots));
     return ok();
 }
 

@@ -76,13 +76,17 @@ struct KJob {
 // Work queues of the split camera render: rays whose walk outlasts
 // split_steps cells are handed on as 1-16 chunks, and chunks that outlast
 // chunk_cap cells hand their remainder on as 1-16 sub-chunks.  Each queue has
-// kSplitRegions regions of kSplitRegionSlots slots, one counter each.
+// kSplitRegions regions of region_slots slots (a multiple of 64), one counter
+// each: kSplitRegionSlots for the queues the library allocates,
+// kNoAllocRegionSlots for the fixed queue of the entry point that allocates
+// nothing.  A walk whose region is full finishes in its own lane, so the size
+// changes the speed, never the result.
 #ifndef PO_SPLIT_REGION_SLOTS
 #define PO_SPLIT_REGION_SLOTS 32768
 #endif
 constexpr int kSplitRegions = 64;
 constexpr int kSplitRegionSlots = PO_SPLIT_REGION_SLOTS;
-constexpr int kSplitSlots = kSplitRegions * kSplitRegionSlots;
+constexpr int kNoAllocRegionSlots = 4096;
 constexpr int kSplitMaxChunks = 16;
 #ifndef PO_SPLIT_STEPS
 #define PO_SPLIT_STEPS 32
@@ -119,14 +123,15 @@ constexpr int kSplitMaxChunks = 16;
 struct KSplit {
     int32_t* count;        // [kSplitRegions] chunk slots claimed (may exceed the region); count2 follows
     int32_t* count2;       // [kSplitRegions] sub-chunk slots claimed
-    int4* info;            // [kSplitSlots] {first chunk slot of the ray (-1: unused), chunk | count << 8, next chunk slot, 0}
-    void* head;            // [kSplitSlots] 32-byte ray states, at the first slot of each ray
-    void* part;            // [kSplitSlots] 32-byte chunk results
-    int4* info2;           // [kSplitSlots] the same for the sub-chunks of remainders
-    void* head2;           // [kSplitSlots] 32-byte remainders, at their first slot
-    void* part2;           // [kSplitSlots] 32-byte sub-chunk results
-    int4* view_part;       // [kSplitSlots] viewer variant: chunk samples, cells and cut flags
-    int4* view_part2;      // [kSplitSlots] the same for the sub-chunks
+    int4* info;            // [slots] {first chunk slot of the ray (-1: unused), chunk | count << 8, next chunk slot, 0}
+    void* head;            // [slots] 32-byte ray states, at the first slot of each ray
+    void* part;            // [slots] 32-byte chunk results
+    int4* info2;           // [slots] the same for the sub-chunks of remainders
+    void* head2;           // [slots] 32-byte remainders, at their first slot
+    void* part2;           // [slots] 32-byte sub-chunk results
+    int4* view_part;       // [slots] viewer variant: chunk samples, cells and cut flags
+    int4* view_part2;      // [slots] the same for the sub-chunks
+    int32_t region_slots;  // slots per region; slots = kSplitRegions * region_slots
     int32_t split_steps;   // cells walked before a ray is handed on
     int32_t chunk_steps;   // target cells per chunk
     int32_t sub_steps;     // target cells per sub-chunk
@@ -136,8 +141,14 @@ struct KSplit {
     const float* ray_d;    // ray-list renders: directions [n_rays][3]
     int64_t n_rays;
 };
-// Device bytes of the queues (counters, then info, head, part of each).
-constexpr size_t kSplitBytes = 512 + 2 * (size_t)kSplitSlots * (16 + 32 + 32 + 16);
+// Device bytes of the queues with region_slots slots per region (counters,
+// then info, head, part and viewer record of each queue).
+constexpr size_t po_split_bytes(int region_slots) {
+    return 512 + 2 * (size_t)kSplitRegions * (size_t)region_slots * (16 + 32 + 32 + 16);
+}
+// Points S at queues laid out in `base` (po_split_bytes(region_slots) bytes)
+// and sets the default piece sizes.
+void po_split_layout(void* base, int region_slots, KSplit* S);
 
 struct po_tree {
     po_tree_desc desc;
@@ -184,6 +195,12 @@ hipError_t po_launch_camera_rays(const KCam& cam, float* o, float* d, hipStream_
 // Visibility filter: mode 0 alpha, 1 contribution; weight[n_leaves] raised in place, alpha[H*W] or nullptr.
 hipError_t po_launch_leaf_weights(const po_tree* t, const KCam& cam, const KOpts& op, int mode, float* weight,
                                   float* alpha, hipStream_t s);
+// Traversal statistics: writes h_sums[4] = {rays, samples, cells,
+// child-entry loads} of the one-pass walk of every pixel ray of *cam, or
+// (cam NULL) of the n rays (o, d), waiting for the stream.  Calls must not
+// overlap (one device buffer).
+hipError_t po_traversal_stats_sync(const po_tree* t, const KCam* cam, int64_t n, const float* o, const float* d,
+                                   const KOpts& op, unsigned long long* h_sums, hipStream_t s);
 hipError_t po_launch_mse_grad(int64_t n, const float* rgb, const float* target, float scale, float* grad,
                               float* sq_sum, hipStream_t s);
 hipError_t po_launch_sgd(int64_t n, float* param, float* grad, float lr, bool zero_grad, hipStream_t s);

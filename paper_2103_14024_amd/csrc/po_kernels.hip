@@ -28,9 +28,22 @@
 
 #include "po_internal.h"
 
-__device__ unsigned long long g_po_errors = 0;
+// The library is built from this file compiled once per part (PO_PART = 0 ..
+// PO_PARTS - 1), in parallel: each part instantiates the kernels of some of
+// the launchers below.  Device variables are per part, so each part keeps its
+// own error counter and part 0 sums them.
+#ifndef PO_PART
+#error "compile with -DPO_PART=<n>, 0 <= n < PO_PARTS"
+#endif
+#define PO_PARTS 8
 
 namespace {
+// malformed child entries and step-cap hits met by this part's kernels
+__device__ unsigned long long g_po_errors = 0;
+#if PO_PART == 0
+// sums of po_traversal_stats: rays, samples, cells, child-entry loads
+__device__ unsigned long long g_po_stats[4];
+#endif
 
 // One wave64 per workgroup: rays finish unevenly, and single-wave workgroups
 // let the dispatcher refill a SIMD as soon as any wave retires, which
@@ -284,7 +297,7 @@ __device__ __forceinline__ void clip_range(const KOpts& op, const double (&o)[3]
     const double p0 = nx * o[0] + ny * o[1] + nz * o[2] + w;
     const double pd = nx * d[0] + ny * d[1] + nz * d[2];
     const double t = -p0 / pd;  // crossing (unused when pd == 0)
-    s_lo = pd > 0.0 ? t : ((pd == 0.0) & (p0 < 0.0) ? 1e300 : 0.0);
+    s_lo = pd > 0.0 ? t : (((pd == 0.0) & (p0 < 0.0)) ? 1e300 : 0.0);
     s_hi = pd < 0.0 ? t : 1e300;
 }
 
@@ -328,6 +341,13 @@ template <class S, class = void>
 struct is_chunk : std::false_type {};
 template <class S>
 struct is_chunk<S, std::void_t<decltype(S::kChunk)>> : std::bool_constant<S::kChunk> {};
+// A sampler with kCountLoads set counts the child entries the walk reads
+// from memory (member `loads`); the out-of-range prefetch after the last
+// step reads nothing and is not counted.
+template <class S, class = void>
+struct counts_loads : std::false_type {};
+template <class S>
+struct counts_loads<S, std::void_t<decltype(S::kCountLoads)>> : std::bool_constant<S::kCountLoads> {};
 
 template <class Sampler, bool SPLIT = false>
 __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int* __restrict__ stk,
@@ -341,6 +361,7 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
     int L = 0, node = 0;
     stk[0] = 0;
     int e = __builtin_amdgcn_raw_buffer_load_b32(child, child_slot(r.c, D, 0) << 2, 0, 0);
+    if constexpr (counts_loads<Sampler>::value) smp.loads += 1;
     // an empty gather, so that every path into the loop has the same loads in
     // flight behind the entry (the compiler then waits for the entry alone)
     smp.issue(-1, 0.0f, 0.0f);
@@ -357,6 +378,7 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
                 stk[L * kBlock] = node;
                 e = __builtin_amdgcn_raw_buffer_load_b32(
                     child, ((uint32_t)node << 5) | (child_slot(r.c, D, L) << 2), 0, 0);
+                if constexpr (counts_loads<Sampler>::value) smp.loads += 1;
                 ++L;
                 malformed = (e > 0) & ((L >= D) | (e >= tr.n_nodes));
                 bad |= malformed;
@@ -431,6 +453,7 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
             }
         }
         e = __builtin_amdgcn_raw_buffer_load_b32(child, pf, 0, 0);
+        if constexpr (counts_loads<Sampler>::value) smp.loads += last ? 0 : 1;
         // composite the previous sample (its loads precede the prefetch)
         bool stop = false;
         if (pending) {
@@ -943,7 +966,8 @@ __device__ __forceinline__ int pieces_wanted(const Ray& r, double s_first, int s
 // lane's first slot, or -1 (want == 0, or the region cannot hold the claim:
 // its claimed slots are then marked unused).  Every lane of the wave must
 // call it.
-__device__ __forceinline__ int claim_pieces(int32_t* count, int4* __restrict__ info, int region, int want) {
+__device__ __forceinline__ int claim_pieces(int32_t* count, int4* __restrict__ info, int region, int want,
+                                            int region_slots) {
     const int lane = (int)threadIdx.x;
     int tot = want;
 #pragma unroll
@@ -952,9 +976,9 @@ __device__ __forceinline__ int claim_pieces(int32_t* count, int4* __restrict__ i
     int base = 0;
     if (lane == 0) base = atomicAdd(count + region, tot);
     base = __shfl(base, 0);
-    const int rbase = region * kSplitRegionSlots;
-    if (base + tot > kSplitRegionSlots) {
-        for (int i = base + lane; i < min(base + tot, kSplitRegionSlots); i += kBlock) info[rbase + i].x = -1;
+    const int rbase = region * region_slots;
+    if (base + tot > region_slots) {
+        for (int i = base + lane; i < min(base + tot, region_slots); i += kBlock) info[rbase + i].x = -1;
         return -1;
     }
     const uint64_t below = (1ull << lane) - 1ull;
@@ -1006,7 +1030,7 @@ __device__ __forceinline__ void first_walk(const KJob& J, const KSplit& S, int i
             }
         }
     }
-    const int h = claim_pieces(S.count, S.info, (int)(blockIdx.x % kSplitRegions), want);
+    const int h = claim_pieces(S.count, S.info, (int)(blockIdx.x % kSplitRegions), want, S.region_slots);
     bool handed = false;
     if (want > 0) {
         if (h >= 0) {
@@ -1075,17 +1099,18 @@ __global__ void k_zero_i32(int32_t* __restrict__ p, int n) {
 // region's claimed slots.  Consecutive workgroups take consecutive slots of a
 // region (faster than interleaving the regions: 735 against 1035 us per
 // depth-9 frame).
-__device__ __forceinline__ int split_slot(const int32_t* count, int first = 0) {
+__device__ __forceinline__ int split_slot(const int32_t* count, int region_slots, int first = 0) {
     const int b = (int)blockIdx.x - first;
-    const int region = b / (kSplitRegionSlots / kBlock);
-    const int local = (b % (kSplitRegionSlots / kBlock)) * kBlock + (int)threadIdx.x;
-    const int n = min(count[region], kSplitRegionSlots);
-    return local < n ? region * kSplitRegionSlots + local : -1;
+    const int per = region_slots / kBlock;  // workgroups per region
+    const int region = b / per;
+    const int local = (b - region * per) * kBlock + (int)threadIdx.x;
+    const int n = min(count[region], region_slots);
+    return local < n ? region * region_slots + local : -1;
 }
 
 template <typename T, int K, int VEC, int NL, int V, int SRC>
 __global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S) {
-    const int q = split_slot(S.count);
+    const int q = split_slot(S.count, S.region_slots);
     const int4 in = q < 0 ? make_int4(-1, 0, -1, 0) : S.info[q];
     const int h = in.x;
     const KJob& J = B.job[0];
@@ -1118,7 +1143,7 @@ __global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S)
             }
         }
     }
-    int sub = claim_pieces(S.count2, S.info2, (int)(blockIdx.x % kSplitRegions), want);
+    int sub = claim_pieces(S.count2, S.info2, (int)(blockIdx.x % kSplitRegions), want, S.region_slots);
     if (want > 0) {
         if (sub >= 0) {
             SubHead sh;
@@ -1151,7 +1176,7 @@ __global__ __launch_bounds__(kBlock) void k_render_chunks(KBatch<1> B, KSplit S)
 
 template <typename T, int K, int VEC, int NL, int V, int SRC>
 __global__ __launch_bounds__(kBlock) void k_render_subchunks(KBatch<1> B, KSplit S) {
-    const int q = split_slot(S.count2);
+    const int q = split_slot(S.count2, S.region_slots);
     if (q < 0) return;
     const int4 in = S.info2[q];
     const int h = in.x;
@@ -1244,7 +1269,7 @@ __device__ __forceinline__ bool join_piece(const KJob& J, const KSplit& S, int p
 
 template <typename T, int K, int VEC, int NL, int V, int SRC>
 __global__ __launch_bounds__(kBlock) void k_render_join(KBatch<1> B, KSplit S) {
-    const int q = split_slot(S.count);
+    const int q = split_slot(S.count, S.region_slots);
     if (q < 0) return;
     const int4 in = S.info[q];
     if (in.x != q) return;  // not the first slot of a ray
@@ -1523,7 +1548,7 @@ __global__ __launch_bounds__(kBlock) void k_backward_split(KBatch<1> B, KSplit S
                 want = pieces_wanted(r, s_first, steps, S, S.chunk_steps);
         }
     }
-    const int h = claim_pieces(S.count, S.info, (int)(blockIdx.x % kSplitRegions), want);
+    const int h = claim_pieces(S.count, S.info, (int)(blockIdx.x % kSplitRegions), want, S.region_slots);
     if (want > 0) {
         if (h >= 0) {
             ContHead hd;
@@ -1572,7 +1597,7 @@ __device__ __forceinline__ void prefix_piece(const KJob& J, const KSplit& S, int
 
 template <int K, int VEC, int NL, int V>
 __global__ __launch_bounds__(kBlock) void k_piece_prefix(KBatch<1> B, KSplit S) {
-    const int q = split_slot(S.count);
+    const int q = split_slot(S.count, S.region_slots);
     if (q < 0) return;
     const int4 in = S.info[q];
     if (in.x != q) return;
@@ -1601,15 +1626,16 @@ __global__ __launch_bounds__(kBlock) void k_piece_prefix(KBatch<1> B, KSplit S) 
     }
 }
 
-// The first kSplitSlots / kBlock workgroups take the walked parts of the
+// The first kSplitRegions * region_slots / kBlock workgroups take the walked parts of the
 // chunks, the others the sub-chunks: the two sets are independent once their
 // prefixes are known, so one launch overlaps their tails.
 template <int K, int VEC, int NL>
 __global__ __launch_bounds__(kBlock) void k_backward_pieces(KBatch<1> B, KSplit S, const float* __restrict__ rgb_fwd,
                                                             const float* __restrict__ grad, float* __restrict__ gsig,
                                                             float* __restrict__ gsh) {
-    const bool sub = blockIdx.x >= (unsigned)(kSplitSlots / kBlock);
-    const int q = split_slot(sub ? S.count2 : S.count, sub ? kSplitSlots / kBlock : 0);
+    const int half = kSplitRegions * (S.region_slots / kBlock);
+    const bool sub = blockIdx.x >= (unsigned)half;
+    const int q = split_slot(sub ? S.count2 : S.count, S.region_slots, sub ? half : 0);
     if (q < 0) return;
     const int4 in = (sub ? S.info2 : S.info)[q];
     if (in.x < 0) return;
@@ -1710,6 +1736,91 @@ __global__ __launch_bounds__(kBlock) void k_leaf_weights(KTree tr, KCam cam, KOp
         Tr = smp.Tl;
     }
     if (alpha) alpha[(size_t)py * cam.W + px] = 1.0f - Tr;
+}
+
+// Traversal statistics of a camera render: the plain walk with a sampler
+// that gathers only the densities (the early stop depends on nothing else;
+// its transmittance arithmetic is the render's, so it stops at the same
+// sample) and counts, per ray, the data samples (segments of positive length
+// in data leaves, as the aux output counts them), the cells visited and the
+// child entries read from memory.  Sums over the image go to sums[4] =
+// {rays, samples, cells, child-entry loads}, one atomic per wave and counter.
+template <typename T>
+struct StatSampler {
+    static constexpr bool kClip = false;
+    static constexpr bool kCountLoads = true;
+    __amdgpu_buffer_rsrc_t sig;
+    uint32_t sig_end;
+    float stopT;
+    float Tl = 1.0f;
+    int ns = 0;
+    int loads = 0;
+    // in flight
+    float raw, delta;
+
+    __device__ __forceinline__ void issue(int l, float d, float) {
+        raw = sigma_buf(sig, l < 0 ? sig_end : (uint32_t)l * (uint32_t)sizeof(T), (T*)nullptr);
+        delta = d;
+    }
+    __device__ __forceinline__ void flush() {}
+    __device__ __forceinline__ bool consume() {
+        ++ns;
+        const float s = fmaxf(raw, 0.0f);
+        if (!(s > 0.0f)) return false;
+        Tl = Tl * __expf(-(s * delta));
+        return Tl < stopT;
+    }
+};
+
+// SRC 0: the pixel rays of cam (16x16 tiles of four 8x8 waves); SRC 1: the
+// n rays (o, d), 64 per wave.
+template <typename T, int SRC>
+__global__ __launch_bounds__(kBlock) void k_traversal_stats(KTree tr, KCam cam, const float* __restrict__ o,
+                                                            const float* __restrict__ d, int64_t n, KOpts op,
+                                                            int n_blocks, unsigned long long* __restrict__ sums) {
+    const int64_t b = xcd_swizzle(blockIdx.x, n_blocks);
+    if (b < 0) return;
+    const int lane = threadIdx.x;
+    bool valid;
+    double ro[3], rd[3];
+    if constexpr (SRC == 0) {
+        const int tiles_x = (cam.W + 15) / 16;
+        const int tile = (int)(b >> 2), quad = (int)(b & 3);
+        const int px = (tile % tiles_x) * 16 + (quad & 1) * 8 + (lane & 7);
+        const int py = (tile / tiles_x) * 16 + (quad >> 1) * 8 + (lane >> 3);
+        valid = (px < cam.W) & (py < cam.H);
+        if (valid) pixel_ray(cam, px, py, ro, rd);
+    } else {
+        const int64_t i = b * kBlock + lane;
+        valid = i < n;
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                ro[k] = (double)o[3 * i + k];
+                rd[k] = (double)d[3 * i + k];
+            }
+        }
+    }
+    unsigned long long v[4] = {valid ? 1ull : 0ull, 0ull, 0ull, 0ull};
+    if (valid) {
+        Ray r;
+        if (ray_setup(tr, ro, rd, r)) {
+            StatSampler<T> smp;
+            smp.sig = raw_rsrc(tr.sigma, tr.sigma_bytes);
+            smp.sig_end = tr.sigma_bytes;
+            smp.stopT = op.stop_T;
+            extern __shared__ int po_stack[];
+            v[2] = (unsigned long long)march(tr, r, op.max_steps, po_stack + threadIdx.x, smp);
+            v[1] = (unsigned long long)smp.ns;
+            v[3] = (unsigned long long)smp.loads;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        unsigned long long x = v[k];
+        for (int o = kBlock / 2; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0 && x != 0ull) atomicAdd(sums + k, x);
+    }
 }
 
 // Loss gradient of the NeRF loss (Sec. 3, eqn:nerfloss) for one batch: one
@@ -1870,7 +1981,7 @@ hipError_t split_t(const po_tree* t, const KJob& job, int n_blocks, int variant,
     // counters cleared by a kernel rather than a memset node, so that the
     // launches can also be captured in a graph
     hipLaunchKernelGGL(k_zero_i32, dim3(2), dim3(kSplitRegions), 0, s, S.count, 2 * kSplitRegions);
-    dim3 g1((unsigned)grid_for(n_blocks)), g2((unsigned)(kSplitSlots / kBlock)), blk(kBlock);
+    dim3 g1((unsigned)grid_for(n_blocks)), g2((unsigned)(kSplitRegions * (S.region_slots / kBlock))), blk(kBlock);
     const size_t lds = stack_bytes(job.tr.depth);
     const bool fast = use_fast<T, K>(t);
 #define PO_SPLIT(VEC_, NL_, V_)                                                                        \
@@ -1929,7 +2040,8 @@ hipError_t backward_split_t(const po_tree* t, int64_t n, const float* o, const f
     S.ray_d = d;
     S.n_rays = n;
     hipLaunchKernelGGL(k_zero_i32, dim3(2), dim3(kSplitRegions), 0, s, S.count, 2 * kSplitRegions);
-    dim3 g1((unsigned)grid_for(B.n_blocks)), g2((unsigned)(kSplitSlots / kBlock)), g3(2u * g2.x), blk(kBlock);
+    dim3 g1((unsigned)grid_for(B.n_blocks)), g2((unsigned)(kSplitRegions * (S.region_slots / kBlock))),
+        g3(2u * g2.x), blk(kBlock);
     const size_t lds = stack_bytes(t->kt.depth);
     const bool sg = t->kt.lobes != nullptr;
     // smaller pieces than the forward's: a backward step costs more (the
@@ -1986,6 +2098,106 @@ hipError_t backward_t(const po_tree* t, int64_t n, const float* o, const float* 
         default: return hipErrorInvalidValue;        \
     }
 
+// Launchers of the parts, by leaf type (defined in the part named).
+hipError_t po_camera_jobs_f32(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, int variant,
+                              hipStream_t s);                                                   // part 1
+hipError_t po_camera_jobs_f16(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, int variant,
+                              hipStream_t s);                                                   // part 2
+hipError_t po_camera_split_f32(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
+                               hipStream_t s);                                                  // part 3
+hipError_t po_camera_split_f16(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
+                               hipStream_t s);                                                  // part 4
+hipError_t po_rays_split_f32(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
+                             hipStream_t s);                                                    // part 5
+hipError_t po_rays_split_f16(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
+                             hipStream_t s);                                                    // part 6
+// Reads (and with reset, clears) part n's error counter; the device is synchronised by the caller.
+#define PO_PART_ERRORS_DECL(n) hipError_t po_part_errors_##n(unsigned long long* out, bool reset);
+PO_PART_ERRORS_DECL(0)
+PO_PART_ERRORS_DECL(1)
+PO_PART_ERRORS_DECL(2)
+PO_PART_ERRORS_DECL(3)
+PO_PART_ERRORS_DECL(4)
+PO_PART_ERRORS_DECL(5)
+PO_PART_ERRORS_DECL(6)
+PO_PART_ERRORS_DECL(7)
+#undef PO_PART_ERRORS_DECL
+
+#define PO_PART_ERRORS_DEF(n)                                                                              \
+    hipError_t po_part_errors_##n(unsigned long long* out, bool reset) {                                  \
+        if (reset) {                                                                                       \
+            const unsigned long long zero = 0ull;                                                          \
+            return hipMemcpyToSymbol(HIP_SYMBOL(g_po_errors), &zero, sizeof(zero), 0, hipMemcpyHostToDevice); \
+        }                                                                                                  \
+        return hipMemcpyFromSymbol(out, HIP_SYMBOL(g_po_errors), sizeof(unsigned long long), 0,            \
+                                   hipMemcpyDeviceToHost);                                                 \
+    }
+
+#if PO_PART == 1
+PO_PART_ERRORS_DEF(1)
+hipError_t po_camera_jobs_f32(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, int variant,
+                              hipStream_t s) {
+    if (n_jobs == 1) {
+        PO_DISPATCH_K(first->K, (camera_t<float, KK, 1>(first, n_jobs, jobs, n_blocks, variant, s)));
+    }
+    PO_DISPATCH_K(first->K, (camera_t<float, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, variant, s)));
+}
+#endif
+
+#if PO_PART == 2
+PO_PART_ERRORS_DEF(2)
+hipError_t po_camera_jobs_f16(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, int variant,
+                              hipStream_t s) {
+    if (n_jobs == 1) {
+        PO_DISPATCH_K(first->K, (camera_t<__half, KK, 1>(first, n_jobs, jobs, n_blocks, variant, s)));
+    }
+    PO_DISPATCH_K(first->K, (camera_t<__half, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, variant, s)));
+}
+#endif
+
+#if PO_PART == 3
+PO_PART_ERRORS_DEF(3)
+hipError_t po_camera_split_f32(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
+                               hipStream_t s) {
+    PO_DISPATCH_K(t->K, (split_t<float, KK, 0>(t, job, n_blocks, variant, S, s)));
+}
+#endif
+
+#if PO_PART == 4
+PO_PART_ERRORS_DEF(4)
+hipError_t po_camera_split_f16(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
+                               hipStream_t s) {
+    PO_DISPATCH_K(t->K, (split_t<__half, KK, 0>(t, job, n_blocks, variant, S, s)));
+}
+#endif
+
+#if PO_PART == 5
+PO_PART_ERRORS_DEF(5)
+hipError_t po_rays_split_f32(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
+                             hipStream_t s) {
+    PO_DISPATCH_K(t->K, (split_t<float, KK, 1>(t, job, n_blocks, variant, S, s)));
+}
+#endif
+
+#if PO_PART == 6
+PO_PART_ERRORS_DEF(6)
+hipError_t po_rays_split_f16(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
+                             hipStream_t s) {
+    PO_DISPATCH_K(t->K, (split_t<__half, KK, 1>(t, job, n_blocks, variant, S, s)));
+}
+#endif
+
+#if PO_PART == 7
+PO_PART_ERRORS_DEF(7)
+hipError_t po_launch_backward_split(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
+                                    const float* rgb_fwd, const float* grad, float* gsig, float* gsh,
+                                    const KSplit& S, hipStream_t s) {
+    PO_DISPATCH_K(t->K, (backward_split_t<KK>(t, n, o, d, op, rgb_fwd, grad, gsig, gsh, S, s)));
+}
+#endif
+
+#if PO_PART == 0
+PO_PART_ERRORS_DEF(0)
 hipError_t po_launch_rays(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
                           float* rgb, float* aux, hipStream_t s) {
     if (t->desc.dtype == PO_F32) {
@@ -1997,27 +2209,14 @@ hipError_t po_launch_rays(const po_tree* t, int64_t n, const float* o, const flo
 
 hipError_t po_launch_camera_jobs(const po_tree* first, int n_jobs, KJob* jobs, int n_blocks, int variant,
                                  hipStream_t s) {
-    if (n_jobs == 1) {
-        if (first->desc.dtype == PO_F32) {
-            PO_DISPATCH_K(first->K, (camera_t<float, KK, 1>(first, n_jobs, jobs, n_blocks, variant, s)));
-        } else {
-            PO_DISPATCH_K(first->K, (camera_t<__half, KK, 1>(first, n_jobs, jobs, n_blocks, variant, s)));
-        }
-    }
-    if (first->desc.dtype == PO_F32) {
-        PO_DISPATCH_K(first->K, (camera_t<float, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, variant, s)));
-    } else {
-        PO_DISPATCH_K(first->K, (camera_t<__half, KK, PO_BATCH_MAX_JOBS>(first, n_jobs, jobs, n_blocks, variant, s)));
-    }
+    return first->desc.dtype == PO_F32 ? po_camera_jobs_f32(first, n_jobs, jobs, n_blocks, variant, s)
+                                       : po_camera_jobs_f16(first, n_jobs, jobs, n_blocks, variant, s);
 }
 
 hipError_t po_launch_camera_split(const po_tree* t, const KJob& job, int n_blocks, int variant, const KSplit& S,
                                   hipStream_t s) {
-    if (t->desc.dtype == PO_F32) {
-        PO_DISPATCH_K(t->K, (split_t<float, KK, 0>(t, job, n_blocks, variant, S, s)));
-    } else {
-        PO_DISPATCH_K(t->K, (split_t<__half, KK, 0>(t, job, n_blocks, variant, S, s)));
-    }
+    return t->desc.dtype == PO_F32 ? po_camera_split_f32(t, job, n_blocks, variant, S, s)
+                                   : po_camera_split_f16(t, job, n_blocks, variant, S, s);
 }
 
 hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
@@ -2042,17 +2241,8 @@ hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, con
     }
     const int n_blocks = (int)((n + kBlock - 1) / kBlock);
     const int variant = po_fwd_variant(op, aux, t->kt);
-    if (t->desc.dtype == PO_F32) {
-        PO_DISPATCH_K(t->K, (split_t<float, KK, 1>(t, job, n_blocks, variant, S, s)));
-    } else {
-        PO_DISPATCH_K(t->K, (split_t<__half, KK, 1>(t, job, n_blocks, variant, S, s)));
-    }
-}
-
-hipError_t po_launch_backward_split(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
-                                    const float* rgb_fwd, const float* grad, float* gsig, float* gsh,
-                                    const KSplit& S, hipStream_t s) {
-    PO_DISPATCH_K(t->K, (backward_split_t<KK>(t, n, o, d, op, rgb_fwd, grad, gsig, gsh, S, s)));
+    return t->desc.dtype == PO_F32 ? po_rays_split_f32(t, job, n_blocks, variant, S, s)
+                                   : po_rays_split_f16(t, job, n_blocks, variant, S, s);
 }
 
 hipError_t po_launch_backward(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
@@ -2080,6 +2270,35 @@ hipError_t po_launch_leaf_weights(const po_tree* t, const KCam& cam, const KOpts
     return hipGetLastError();
 }
 
+hipError_t po_traversal_stats_sync(const po_tree* t, const KCam* cam, int64_t n, const float* o, const float* d,
+                                   const KOpts& op, unsigned long long* h_sums, hipStream_t s) {
+    // the sums live in this part's g_po_stats; the caller serialises calls
+    unsigned long long* d_sums = nullptr;
+    hipError_t e = hipGetSymbolAddress((void**)&d_sums, HIP_SYMBOL(g_po_stats));
+    if (e != hipSuccess) return e;
+    if ((e = hipMemsetAsync(d_sums, 0, 4 * sizeof(unsigned long long), s)) != hipSuccess) return e;
+    KCam c;
+    std::memset(&c, 0, sizeof c);
+    if (cam) c = *cam;
+    const int n_blocks = cam ? 4 * ((c.W + 15) / 16) * ((c.H + 15) / 16) : (int)((n + kBlock - 1) / kBlock);
+    dim3 grid((unsigned)grid_for(n_blocks)), block(kBlock);
+    const size_t lds = stack_bytes(t->kt.depth);
+    const bool f32 = t->desc.dtype == PO_F32;
+    if (cam && f32)
+        hipLaunchKernelGGL((k_traversal_stats<float, 0>), grid, block, lds, s, t->kt, c, o, d, n, op, n_blocks, d_sums);
+    else if (cam)
+        hipLaunchKernelGGL((k_traversal_stats<__half, 0>), grid, block, lds, s, t->kt, c, o, d, n, op, n_blocks, d_sums);
+    else if (f32)
+        hipLaunchKernelGGL((k_traversal_stats<float, 1>), grid, block, lds, s, t->kt, c, o, d, n, op, n_blocks, d_sums);
+    else
+        hipLaunchKernelGGL((k_traversal_stats<__half, 1>), grid, block, lds, s, t->kt, c, o, d, n, op, n_blocks, d_sums);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(h_sums, d_sums, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+        return e;
+    return hipStreamSynchronize(s);
+}
+
 hipError_t po_launch_camera_rays(const KCam& cam, float* o, float* d, hipStream_t s) {
     const int64_t n = (int64_t)cam.W * cam.H;
     hipLaunchKernelGGL(k_camera_rays, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cam, o, d);
@@ -2102,15 +2321,28 @@ hipError_t po_launch_sgd(int64_t n, float* param, float* grad, float lr, bool ze
 hipError_t po_read_device_errors(unsigned long long* out) {
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return e;
-    return hipMemcpyFromSymbol(out, HIP_SYMBOL(g_po_errors), sizeof(unsigned long long), 0,
-                               hipMemcpyDeviceToHost);
+    hipError_t (*const part[PO_PARTS])(unsigned long long*, bool) = {
+        po_part_errors_0, po_part_errors_1, po_part_errors_2, po_part_errors_3,
+        po_part_errors_4, po_part_errors_5, po_part_errors_6, po_part_errors_7};
+    unsigned long long sum = 0;
+    for (int i = 0; i < PO_PARTS; ++i) {
+        unsigned long long v = 0;
+        if ((e = part[i](&v, false)) != hipSuccess) return e;
+        sum += v;
+    }
+    *out = sum;
+    return hipSuccess;
 }
 
 hipError_t po_reset_device_errors() {
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return e;
-    const unsigned long long zero = 0ull;
-    return hipMemcpyToSymbol(HIP_SYMBOL(g_po_errors), &zero, sizeof(zero), 0, hipMemcpyHostToDevice);
+    hipError_t (*const part[PO_PARTS])(unsigned long long*, bool) = {
+        po_part_errors_0, po_part_errors_1, po_part_errors_2, po_part_errors_3,
+        po_part_errors_4, po_part_errors_5, po_part_errors_6, po_part_errors_7};
+    for (int i = 0; i < PO_PARTS; ++i)
+        if ((e = part[i](nullptr, true)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 int po_plan_id(const po_tree* t) {
@@ -2131,3 +2363,4 @@ int po_plan_id(const po_tree* t) {
     }
     return (kind * 64 + t->K) * 2 + (fast ? 1 : 0);
 }
+#endif  // PO_PART == 0

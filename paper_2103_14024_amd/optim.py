@@ -47,31 +47,36 @@ class Trainer:
         self.steps = 0
 
     def step(self, stream=None):
-        """One SGD step; returns the batch loss as a 1-element device tensor
-        (mean squared error over rays and channels)."""
+        """One SGD step on `stream` (None: torch's current stream); returns the
+        batch loss as a 1-element device tensor (mean squared error over rays
+        and channels), valid once the stream has completed.  The batch gather
+        and the loss scaling run on the same stream as the library calls."""
         import torch
 
-        s = _stream_ptr(stream)
+        ts = stream if stream is not None else torch.cuda.current_stream(self.o.device)
+        s = _stream_ptr(ts)
         n = self.batch
-        idx = torch.randint(0, self.o.shape[0], (n,), device=self.o.device, generator=self.gen)
-        torch.index_select(self.o, 0, idx, out=self.bo)
-        torch.index_select(self.d, 0, idx, out=self.bd)
-        torch.index_select(self.t, 0, idx, out=self.bt)
-        self.sq.zero_()
         tr = self.tree
-        L.call("po_render_rays", tr.handle, n, self.bo.data_ptr(), self.bd.data_ptr(), ctypes.byref(self.opts),
-               self.rgb.data_ptr(), None, s)
-        L.call("po_mse_grad", n, self.rgb.data_ptr(), self.bt.data_ptr(), ctypes.c_float(1.0 / (3 * n)),
-               self.grad_rgb.data_ptr(), self.sq.data_ptr(), s)
-        L.call("po_render_rays_backward", tr.handle, n, self.bo.data_ptr(), self.bd.data_ptr(),
-               ctypes.byref(self.opts), self.rgb.data_ptr(), self.grad_rgb.data_ptr(), self.g_sigma.data_ptr(),
-               self.g_sh.data_ptr(), s)
-        L.call("po_sgd_step", tr.sigma.numel(), tr.sigma.data_ptr(), self.g_sigma.data_ptr(),
-               ctypes.c_float(self.lr_sigma), 1, s)
-        L.call("po_sgd_step", tr.sh.numel(), tr.sh.data_ptr(), self.g_sh.data_ptr(), ctypes.c_float(self.lr_sh), 1,
-               s)
+        with torch.cuda.stream(ts):
+            idx = torch.randint(0, self.o.shape[0], (n,), device=self.o.device, generator=self.gen)
+            torch.index_select(self.o, 0, idx, out=self.bo)
+            torch.index_select(self.d, 0, idx, out=self.bd)
+            torch.index_select(self.t, 0, idx, out=self.bt)
+            self.sq.zero_()
+            L.call("po_render_rays", tr.handle, n, self.bo.data_ptr(), self.bd.data_ptr(), ctypes.byref(self.opts),
+                   self.rgb.data_ptr(), None, s)
+            L.call("po_mse_grad", n, self.rgb.data_ptr(), self.bt.data_ptr(), ctypes.c_float(1.0 / (3 * n)),
+                   self.grad_rgb.data_ptr(), self.sq.data_ptr(), s)
+            L.call("po_render_rays_backward", tr.handle, n, self.bo.data_ptr(), self.bd.data_ptr(),
+                   ctypes.byref(self.opts), self.rgb.data_ptr(), self.grad_rgb.data_ptr(), self.g_sigma.data_ptr(),
+                   self.g_sh.data_ptr(), s)
+            L.call("po_sgd_step", tr.sigma.numel(), tr.sigma.data_ptr(), self.g_sigma.data_ptr(),
+                   ctypes.c_float(self.lr_sigma), 1, s)
+            L.call("po_sgd_step", tr.sh.numel(), tr.sh.data_ptr(), self.g_sh.data_ptr(),
+                   ctypes.c_float(self.lr_sh), 1, s)
+            loss = self.sq / (3 * n)
         self.steps += 1
-        return self.sq / (3 * n)
+        return loss
 
 
 def training_set(gt_tree, cams, bg=(1.0, 1.0, 1.0), stop_T=1e-4, device="cuda"):

@@ -22,15 +22,17 @@ AUX_T, AUX_SAMPLES, AUX_STEPS, AUX_DEPTH = 0, 1, 2, 3
 AUX_WIDTH = 4
 
 
-def make_opts(bg=(1.0, 1.0, 1.0), stop_T=1e-4, max_steps=0, aux=False, sh_off=0, clip=None) -> L.po_render_opts:
+def make_opts(bg=(1.0, 1.0, 1.0), stop_T=1e-4, max_steps=0, aux=False, sh_off=0, clip=None,
+              one_pass=False) -> L.po_render_opts:
     """Render options.  sh_off: bit k leaves out SH basis function k; clip:
-    slicing plane (nx, ny, nz, w), only n.x + w >= 0 is rendered."""
+    slicing plane (nx, ny, nz, w), only n.x + w >= 0 is rendered; one_pass:
+    every ray walked to its end by one lane, never in pieces."""
     o = L.po_render_opts()
     for k in range(3):
         o.bg[k] = float(bg[k])
     o.stop_T = float(stop_T)
     o.max_steps = int(max_steps)
-    o.flags = L.PO_OUT_AUX if aux else 0
+    o.flags = (L.PO_OUT_AUX if aux else 0) | (L.PO_ONE_PASS if one_pass else 0)
     o.sh_off = int(sh_off) & 0xFFFFFFFF
     if clip is not None:
         c = [float(v) for v in clip]
@@ -87,7 +89,7 @@ class Camera:
 
 
 def render_rays(tree, origins, dirs, bg=(1.0, 1.0, 1.0), stop_T=1e-4, aux=False, max_steps=0, out=None,
-                aux_out=None, stream=None, sh_off=0, clip=None):
+                aux_out=None, stream=None, sh_off=0, clip=None, one_pass=False):
     """Colours (n, 3) of rays (origins, dirs: float32 (n, 3) device tensors);
     with aux also the (n, 4) columns AUX_T, AUX_SAMPLES, AUX_STEPS, AUX_DEPTH."""
     torch = _torch()
@@ -102,14 +104,14 @@ def render_rays(tree, origins, dirs, bg=(1.0, 1.0, 1.0), stop_T=1e-4, aux=False,
     if aux:
         a = _out(aux_out, (n, AUX_WIDTH), "aux_out") if aux_out is not None else torch.empty(
             (n, AUX_WIDTH), dtype=torch.float32, device=origins.device)
-    opts = make_opts(bg, stop_T, max_steps, aux, sh_off, clip)
+    opts = make_opts(bg, stop_T, max_steps, aux, sh_off, clip, one_pass)
     L.call("po_render_rays", tree.handle, n, origins.data_ptr(), dirs.data_ptr(), ctypes.byref(opts),
            rgb.data_ptr(), a.data_ptr() if a is not None else None, _stream_ptr(stream))
     return (rgb, a) if aux else rgb
 
 
 def render_camera(tree, cam: Camera, bg=(1.0, 1.0, 1.0), stop_T=1e-4, aux=False, max_steps=0, out=None,
-                  aux_out=None, stream=None, device="cuda", sh_off=0, clip=None):
+                  aux_out=None, stream=None, device="cuda", sh_off=0, clip=None, one_pass=False):
     """Image (H, W, 3) of a camera; with aux also (H, W, 4) aux columns."""
     torch = _torch()
     shape = (cam.height, cam.width, 3)
@@ -119,7 +121,7 @@ def render_camera(tree, cam: Camera, bg=(1.0, 1.0, 1.0), stop_T=1e-4, aux=False,
         ashape = (cam.height, cam.width, AUX_WIDTH)
         a = _out(aux_out, ashape, "aux_out") if aux_out is not None else torch.empty(
             ashape, dtype=torch.float32, device=device)
-    opts = make_opts(bg, stop_T, max_steps, aux, sh_off, clip)
+    opts = make_opts(bg, stop_T, max_steps, aux, sh_off, clip, one_pass)
     c = cam.to_c()
     L.call("po_render_camera", tree.handle, ctypes.byref(c), ctypes.byref(opts), img.data_ptr(),
            a.data_ptr() if a is not None else None, _stream_ptr(stream))
@@ -138,19 +140,29 @@ def camera_rays(cam: Camera, stream=None, device="cuda"):
 
 
 def render_rays_backward(tree, origins, dirs, rgb_fwd, grad_rgb, bg=(1.0, 1.0, 1.0), stop_T=1e-4, max_steps=0,
-                         grad_sigma=None, grad_sh=None, stream=None):
+                         grad_sigma=None, grad_sh=None, stream=None, one_pass=False):
     """Accumulates dL/dsigma (n_leaves,) and dL/dsh (n_leaves, stride); returns both."""
     torch = _torch()
     _rays3(origins, "origins")
     _rays3(dirs, "dirs")
     _rays3(rgb_fwd, "rgb_fwd")
     _rays3(grad_rgb, "grad_rgb")
+    n = origins.shape[0]
+    for t, name in ((dirs, "dirs"), (rgb_fwd, "rgb_fwd"), (grad_rgb, "grad_rgb")):
+        if t.shape[0] != n:
+            raise ValueError(f"{name} has {t.shape[0]} rows, origins {n}")
+    # the kernels add into grad_sigma[leaf] and grad_sh[leaf * stride + e]
+    shape_sh = (tree.n_leaves, tree.stride)
     if grad_sigma is None:
-        grad_sigma = torch.zeros_like(tree.sigma, dtype=torch.float32)
+        grad_sigma = torch.zeros((tree.n_leaves,), dtype=torch.float32, device=origins.device)
+    else:
+        _out(grad_sigma, (tree.n_leaves,), "grad_sigma")
     if grad_sh is None:
-        grad_sh = torch.zeros_like(tree.sh, dtype=torch.float32)
-    opts = make_opts(bg, stop_T, max_steps)
-    L.call("po_render_rays_backward", tree.handle, origins.shape[0], origins.data_ptr(), dirs.data_ptr(),
+        grad_sh = torch.zeros(shape_sh, dtype=torch.float32, device=origins.device)
+    else:
+        _out(grad_sh, shape_sh, "grad_sh")
+    opts = make_opts(bg, stop_T, max_steps, one_pass=one_pass)
+    L.call("po_render_rays_backward", tree.handle, n, origins.data_ptr(), dirs.data_ptr(),
            ctypes.byref(opts), rgb_fwd.data_ptr(), grad_rgb.data_ptr(), grad_sigma.data_ptr(), grad_sh.data_ptr(),
            _stream_ptr(stream))
     return grad_sigma, grad_sh
@@ -209,10 +221,12 @@ class Job:
     aux_out: object = None  # (H, W, 4) float32 device tensor or None
     sh_off: int = 0
     clip: object = None
+    one_pass: bool = False  # never in pieces (jobs of >= 256 tiles otherwise are)
 
 
 def render_batch(jobs, stream=None) -> None:
-    """Renders up to 16 camera jobs (any trees, any sizes, tile sub-ranges)."""
+    """Renders up to 16 camera jobs (any trees, any sizes, tile sub-ranges);
+    jobs of 256 tiles or more are rendered in pieces unless one_pass is set."""
     arr = (L.po_job * max(1, len(jobs)))()
     for i, j in enumerate(jobs):
         _out(j.out, (j.cam.height, j.cam.width, 3), "Job.out")
@@ -220,12 +234,32 @@ def render_batch(jobs, stream=None) -> None:
             _out(j.aux_out, (j.cam.height, j.cam.width, AUX_WIDTH), "Job.aux_out")
         arr[i].tree = j.tree.handle.value
         arr[i].cam = j.cam.to_c()
-        arr[i].opts = make_opts(j.bg, j.stop_T, 0, j.aux_out is not None, j.sh_off, j.clip)
+        arr[i].opts = make_opts(j.bg, j.stop_T, 0, j.aux_out is not None, j.sh_off, j.clip, j.one_pass)
         arr[i].d_rgb = j.out.data_ptr()
         arr[i].d_aux = j.aux_out.data_ptr() if j.aux_out is not None else None
         arr[i].tile_begin = int(j.tile_begin)
         arr[i].tile_end = int(j.cam.n_tiles if j.tile_end < 0 else j.tile_end)
     L.call("po_render_batch", len(jobs), arr, _stream_ptr(stream))
+
+
+def traversal_stats(tree, cam=None, origins=None, dirs=None, stop_T=1e-4, max_steps=0, stream=None) -> dict:
+    """Unit counts of the one-pass walk of a camera's pixel rays, or of the
+    rays (origins, dirs), waiting for the stream: rays, data samples, cells
+    visited and child entries read."""
+    v = (ctypes.c_int64 * 4)()
+    opts = make_opts((1.0, 1.0, 1.0), stop_T, max_steps)
+    if cam is not None:
+        c = cam.to_c()
+        L.call("po_traversal_stats", tree.handle, ctypes.byref(c), ctypes.byref(opts),
+               ctypes.cast(v, ctypes.c_void_p), _stream_ptr(stream))
+    else:
+        _rays3(origins, "origins")
+        _rays3(dirs, "dirs")
+        if dirs.shape[0] != origins.shape[0]:
+            raise ValueError("origins and dirs differ in length")
+        L.call("po_traversal_stats_rays", tree.handle, origins.shape[0], origins.data_ptr(), dirs.data_ptr(),
+               ctypes.byref(opts), ctypes.cast(v, ctypes.c_void_p), _stream_ptr(stream))
+    return {"rays": int(v[0]), "samples": int(v[1]), "cells": int(v[2]), "node_loads": int(v[3])}
 
 
 def device_errors() -> int:
@@ -236,6 +270,12 @@ def device_errors() -> int:
 
 def reset_device_errors() -> None:
     L.call("po_device_errors_reset")
+
+
+def reserve_queues(stream=None) -> None:
+    """Allocates the split-render work queue of `stream` now (torch's current
+    stream by default), so that no later render on it allocates."""
+    L.call("po_reserve_queues", _stream_ptr(stream))
 
 
 def release_queues() -> None:

@@ -1,14 +1,17 @@
 """Continuous-batching render server over several scenes resident in HBM.
 
 Requests (scene, camera) arrive over time.  The loop admits arrived requests
-while their output images fit an HBM budget and a slot cap, cuts every
-admitted request into chunks of 16x16 tiles, and packs chunks of several
-requests -- of any scene and resolution -- into batched launches
-(po_render_batch, up to 16 jobs each) on a few HIP streams.  Requests that
-arrive while others are in flight join the next launch; a large frame never
-blocks a small one for longer than one chunk.  A request is complete when the
-last launch holding one of its tiles has finished; latency is measured from
-its arrival to that launch's completion on the GPU clock (HIP events).
+while their output images fit an HBM budget and a slot cap.  A request of at
+least `split_tiles` 16x16 tiles is rendered whole by one job, which the
+library renders in pieces (long walks cut and walked in parallel); smaller
+requests are cut into chunks of tiles, and chunks of several requests -- of
+any scene and resolution -- are packed into batched launches
+(po_render_batch, up to 16 jobs each).  Launches go round-robin to a few HIP
+streams, so a large frame and the batches of small ones run on the device
+together.  Requests that arrive while others are in flight join the next
+launch.  A request is complete when the last launch holding one of its tiles
+has finished; latency is measured from its arrival to that launch's
+completion on the GPU clock (HIP events).
 
 The rendering itself is the library's; this module is scheduling only.
 """
@@ -95,6 +98,8 @@ class Stats:
     pixels: int = 0
     launches: int = 0
     jobs: int = 0
+    max_jobs: int = 0                   # most jobs in one launch
+    whole: int = 0                      # requests rendered whole, in pieces
     max_active: int = 0
     max_bytes: int = 0
 
@@ -104,7 +109,8 @@ class Stats:
                 "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
                 "throughput_req_s": round(len(lat) / self.wall_s, 2),
                 "mrays_per_s": round(self.pixels / self.wall_s / 1e6, 2), "launches": self.launches,
-                "jobs_per_launch": round(self.jobs / max(1, self.launches), 2), "max_active": self.max_active,
+                "jobs_per_launch": round(self.jobs / max(1, self.launches), 2), "max_jobs_per_launch": self.max_jobs,
+                "rendered_whole": self.whole, "max_active": self.max_active,
                 "max_output_mb": round(self.max_bytes / 1e6, 1)}
 
 
@@ -114,10 +120,11 @@ class Server:
     trees: resident scenes; budget_bytes: HBM for output images; max_active:
     admitted-request slots; chunk_tiles: least tiles of one request per
     launch; launch_tiles: tiles per launch; streams: HIP streams used round-robin;
-    max_inflight: launches queued on the GPU at once."""
+    max_inflight: launches queued on the GPU at once; split_tiles: requests of
+    at least this many tiles are rendered whole, in pieces (None: never)."""
 
     def __init__(self, trees, budget_bytes=512 << 20, max_active=64, chunk_tiles=256, launch_tiles=2048,
-                 streams=3, max_inflight=4, stop_T=1e-4, bg=(1.0, 1.0, 1.0), device="cuda"):
+                 streams=3, max_inflight=4, stop_T=1e-4, bg=(1.0, 1.0, 1.0), device="cuda", split_tiles=1024):
         import torch
 
         self.trees = list(trees)
@@ -126,6 +133,7 @@ class Server:
         self.streams = [torch.cuda.Stream(device=device) for _ in range(streams)]
         self.max_inflight = max_inflight
         self.stop_T, self.bg = stop_T, tuple(bg)
+        self.split_tiles = split_tiles if split_tiles is not None else 1 << 30
 
     def run(self, requests, keep_images=False, on_complete=None) -> Stats:
         """Serves `requests` (sorted by arrival) in real time; returns Stats."""
@@ -184,11 +192,27 @@ class Server:
             # shared among the requests with work left, but no request gets less
             # than chunk_tiles (so a lone request still fills the GPU)
             if len(inflight) < self.max_inflight:
+                # the oldest large request not started yet: whole, in pieces
+                big = next((r for r in active if r.next_tile == 0 and r.tiles >= self.split_tiles), None)
+                if big is not None:
+                    s = self.streams[k_stream % len(self.streams)]
+                    k_stream += 1
+                    render_batch([Job(self.trees[big.scene], big.cam, self.arena.view(big), 0, big.tiles, self.bg,
+                                      self.stop_T)], stream=s)
+                    big.next_tile = big.tiles
+                    ev = torch.cuda.Event(enable_timing=True)
+                    ev.record(s)
+                    inflight.append((ev, [(big, big.tiles)]))
+                    st.launches += 1
+                    st.jobs += 1
+                    st.whole += 1
+                    st.max_jobs = max(st.max_jobs, 1)
+                    continue
                 jobs, parts, budget = [], [], self.launch_tiles
                 n_open = sum(1 for r in active if r.next_tile < r.tiles)
                 share = max(self.chunk_tiles, self.launch_tiles // max(1, n_open))
                 for req in active:
-                    if req.next_tile >= req.tiles:
+                    if req.next_tile >= req.tiles or (req.next_tile == 0 and req.tiles >= self.split_tiles):
                         continue
                     n = min(share, req.tiles - req.next_tile, budget)
                     if n <= 0 or len(jobs) == L.PO_BATCH_MAX_JOBS:
@@ -207,6 +231,7 @@ class Server:
                     inflight.append((ev, parts))
                     st.launches += 1
                     st.jobs += len(jobs)
+                    st.max_jobs = max(st.max_jobs, len(jobs))
                     continue
             if not inflight and not active and not waiting and pending:
                 dt = pending[0].arrival - (time.perf_counter() - t0)

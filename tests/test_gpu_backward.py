@@ -121,3 +121,34 @@ def test_autograd_function(po):
     _compare(gsh, rsh, "autograd dsh")
     # padding columns of the SH records receive no gradient
     assert tree.sh.grad[:, 27:].abs().max().item() == 0.0
+
+
+def test_backward_rejects_mis_sized_buffers(po):
+    # every caller-supplied buffer is checked before the library is called:
+    # a short or wrongly typed gradient buffer would be written out of bounds
+    import torch
+
+    s = _scene(4, 1, 51)
+    tree = po.Tree.from_scene(s)
+    o, d = scenes.random_rays(100, 9, spread=1.0)
+    og, dg = _dev(o), _dev(d)
+    rgb = po.render_rays(tree, og, dg)
+    g = torch.ones_like(rgb)
+    bad = [
+        dict(grad_sigma=torch.zeros(tree.n_leaves - 1, device="cuda")),
+        dict(grad_sigma=torch.zeros(tree.n_leaves, device="cuda", dtype=torch.float16)),
+        dict(grad_sh=torch.zeros((tree.n_leaves, tree.stride - 1), device="cuda")),
+        dict(grad_sh=torch.zeros((tree.n_leaves, tree.stride), device="cuda").t()),
+        dict(grad_sh=torch.zeros((tree.n_leaves, tree.stride), device="cpu")),
+    ]
+    for kw in bad:
+        with pytest.raises(ValueError):
+            po.render_rays_backward(tree, og, dg, rgb, g, **kw)
+    with pytest.raises(ValueError):
+        po.render_rays_backward(tree, og, dg[:99].contiguous(), rgb, g)
+    with pytest.raises(ValueError):
+        po.render_rays_backward(tree, og, dg, rgb[:99].contiguous(), g)
+    with pytest.raises(ValueError):
+        po.render_rays_backward(tree, og, dg, rgb, g[:99].contiguous())
+    gs, gsh = po.render_rays_backward(tree, og, dg, rgb, g)
+    assert tuple(gs.shape) == (tree.n_leaves,) and tuple(gsh.shape) == (tree.n_leaves, tree.stride)

@@ -1,6 +1,8 @@
-"""The render server: every image produced in the batched, continuously
-admitted mix equals the same request rendered alone in one launch (bit-identical), and
-admission never exceeds the output-memory budget or the slot cap."""
+"""The render server: every image produced in the continuously admitted mix
+equals the same request rendered alone by one job (bit-identical), whether
+it was batched with other requests in one-pass launches or rendered whole in
+pieces, and admission never exceeds the output-memory budget or the slot
+cap."""
 import sys
 
 import numpy as np
@@ -21,7 +23,11 @@ def po():
     return po
 
 
-def test_alone_equals_mix(po):
+@pytest.mark.parametrize("split_tiles", [None, 1024])
+def test_alone_equals_mix(po, split_tiles):
+    # split_tiles None: every request cut into tile chunks and batched; 1024:
+    # requests of 512x512 pixels or more rendered whole, in pieces, on their
+    # own, the 256x256 ones batched
     from paper_2103_14024_amd import server
 
     sc = [scenes.scene_small(), scenes.scene_blobs(depth=6, sh_degree=3, seed=2, data_seed=3),
@@ -30,20 +36,28 @@ def test_alone_equals_mix(po):
              po.Tree.from_scene(sc[2], dtype="f32")]
     reqs = server.poisson_requests(60, 400.0, 3, seed=9)
     budget = 40 << 20   # forces queueing behind the memory budget (a 1080p image takes 24.9 MB)
-    srv = server.Server(trees, budget_bytes=budget, max_active=6, chunk_tiles=64, launch_tiles=512, streams=3)
+    srv = server.Server(trees, budget_bytes=budget, max_active=6, chunk_tiles=64, launch_tiles=512, streams=3,
+                        split_tiles=split_tiles)
     st = srv.run(reqs, keep_images=True)
     s = st.summary()
-    print(f"[gpu] server: {s}", file=sys.stderr, flush=True)
+    print(f"[gpu] server (split_tiles {split_tiles}): {s}", file=sys.stderr, flush=True)
     assert s["requests"] == 60 and st.max_active <= 6 and st.max_bytes <= budget
-    assert s["jobs_per_launch"] > 1.0
+    if split_tiles is None:
+        assert s["jobs_per_launch"] > 1.0 and st.whole == 0
+    else:
+        assert st.whole == sum(1 for r in reqs if r.cam.n_tiles >= split_tiles) > 0
     import torch
 
     for r in reqs:
-        # the request rendered alone in one batched launch (render_camera
-        # splits large images, which reorders the float sums)
+        # the request rendered alone by one job of the whole image, in one pass
+        # or in pieces as in the mix
+        whole = split_tiles is not None and r.cam.n_tiles >= split_tiles
         alone = torch.empty((r.cam.height, r.cam.width, 3), device="cuda")
-        po.render_batch([po.Job(trees[r.scene], r.cam, alone)])
+        po.render_batch([po.Job(trees[r.scene], r.cam, alone, one_pass=not whole)])
+        # bit for bit: a batched job walks each ray in one lane; a whole
+        # request's pieces depend on its rays only
         assert np.array_equal(alone.cpu().numpy(), r.image), r.rid
         if r.cam.width * r.cam.height >= 1 << 16:
-            assert np.abs(po.render_camera(trees[r.scene], r.cam).cpu().numpy() - r.image).max() <= 1.1e-4, r.rid
+            ref = po.render_camera(trees[r.scene], r.cam).cpu().numpy()
+            assert np.abs(ref - r.image).max() <= (0.0 if whole else 1.1e-4), r.rid
         assert r.t_done >= r.arrival

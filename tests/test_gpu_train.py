@@ -78,3 +78,52 @@ def test_training_reduces_loss(po):
           f"{np.mean(losses[-10:]):.3e}", file=sys.stderr, flush=True)
     assert m1 < 0.5 * m0
     assert np.mean(losses[-10:]) < np.mean(losses[:10])
+
+
+def test_trainer_step_matches_oracle_update(po):
+    # one Trainer step (65536-ray batch: the split backward) with distinct
+    # learning rates for densities and coefficients, on its own stream: the
+    # parameter change divided by each learning rate must be the FP64 oracle
+    # gradient of the mean squared error over the batch (threshold-straddle
+    # rule at stop_T), and the gradient buffers are cleared by the step
+    import torch
+
+    import gradcheck
+    import oracle
+
+    gt = scenes.scene_blobs(depth=6, sh_degree=2, seed=4, data_seed=5)
+    tgt_tree = po.Tree.from_scene(gt)
+    fx, fy, cx, cy = scenes.intrinsics(96, 96, 40.0)
+    cams = [po.Camera(p, 96, 96, fx, fy, cx, cy) for p in scenes.hemisphere_poses(12, 4.0, 6)]
+    o, d, t = po.optim.training_set(tgt_tree, cams)
+    sig, sh = scenes.perturb(gt["sigma"], gt["sh"], 0.3, 8)
+    tree = po.Tree.from_cells(gt["depth"], 2, gt["cells"], sig, sh)
+    sig0 = tree.sigma.detach().clone()
+    sh0 = tree.sh.detach().clone()
+    lr_s, lr_h = 1.0e7, 2.5e6
+    tr = po.Trainer(tree, o, d, t, lr_sigma=lr_s, lr_sh=lr_h, batch=65536, seed=3)
+    stream = torch.cuda.Stream()
+    loss = tr.step(stream=stream)
+    stream.synchronize()
+    # the batch the step drew, its forward colours and upstream gradient
+    bo, bd = tr.bo.cpu().numpy(), tr.bd.cpu().numpy()
+    rgb, bt = tr.rgb.cpu().numpy().astype(np.float64), tr.bt.cpu().numpy().astype(np.float64)
+    g = tr.grad_rgb.cpu().numpy().astype(np.float64)
+    n = tr.batch
+    assert np.allclose(g, 2.0 * (rgb - bt) / (3 * n), rtol=1e-6, atol=1e-15)
+    assert abs(float(loss) - float(((rgb - bt) ** 2).mean())) <= 1e-5 * float(((rgb - bt) ** 2).mean())
+    assert float(tr.g_sigma.abs().max()) == 0.0 and float(tr.g_sh.abs().max()) == 0.0
+    ot = oracle.OracleTree(gt["depth"], 2, gt["center"], gt["half"], gt["cells"], sig, sh)
+    (ls, hs), (lh, hh), n_str = gradcheck.grad_envelope(ot, bo, bd, g, (1.0, 1.0, 1.0), 1e-4)
+    print(f"[gpu] trainer step: {n_str} straddling rays", file=sys.stderr, flush=True)
+    # p' = fl(p - lr g): the change over lr carries half an ulp of p' over lr
+    s1, h1 = tree.sigma.detach().double().cpu().numpy(), tree.sh.detach().double().cpu().numpy()
+    s0, h0 = sig0.double().cpu().numpy(), sh0.double().cpu().numpy()
+    est_s, est_h = gradcheck.to_cells(tree, (s0 - s1) / lr_s, (h0 - h1) / lr_h)
+    ulp_s, ulp_h = gradcheck.to_cells(tree, np.spacing(np.abs(s1).astype(np.float32)) / lr_s,
+                                      np.spacing(np.abs(h1).astype(np.float32)) / lr_h)
+    K = tree.K
+    # padding columns of the records are not touched
+    assert np.array_equal(h1[:, 3 * K:], h0[:, 3 * K:])
+    gradcheck.check(est_s, ls, hs, "trainer step dsigma", slack=0.5 * ulp_s)
+    gradcheck.check(est_h, lh, hh, "trainer step dsh", slack=0.5 * ulp_h)
