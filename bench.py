@@ -97,19 +97,19 @@ def measure(po, tree, cams, steps, warmup, stream, aux_pass=True):
     order = timed_poses(steps, len(cams))
     poses = sorted(set(order))
     # per-pose unit counts of the walk (samples, cells, child-entry reads) and
-    # lane efficiency, outside the timed region
+    # lane efficiency of the one-pass walk, outside the timed region
     aux = torch.empty((H, W, po.AUX_WIDTH), dtype=torch.float32, device="cuda")
     stats, wave_iters = {}, []
     for p in (poses if aux_pass else []):
         stats[p] = po.traversal_stats(tree, cams[p], stop_T=STOP_T, stream=stream)
-        po.render_camera(tree, cams[p], stop_T=STOP_T, aux=True, out=img, aux_out=aux, stream=stream)
-        a = aux.view(-1, po.AUX_WIDTH).sum(0).cpu()
-        # the aux output of the render counts the same samples and cells
+        po.render_camera(tree, cams[p], stop_T=STOP_T, aux=True, out=img, aux_out=aux, stream=stream, one_pass=True)
+        a = aux.view(-1, po.AUX_WIDTH).double().sum(0).cpu()  # counts above 2^24: sum in float64
+        # the aux output of the one-pass render counts the same samples and cells
         assert int(a[po.AUX_SAMPLES]) == stats[p]["samples"] and int(a[po.AUX_STEPS]) == stats[p]["cells"], p
         # SIMD efficiency of the traversal loop: a wave (8x8 pixels) runs as
         # many iterations as its slowest lane
         st = aux[..., po.AUX_STEPS].view(H // 8, 8, W // 8, 8).amax(dim=(1, 3))
-        wave_iters.append(float(st.sum()) * 64)
+        wave_iters.append(float(st.double().sum()) * 64)
     for i in range(warmup):
         po.render_camera(tree, cams[i % len(cams)], stop_T=STOP_T, out=img, stream=stream)
     torch.cuda.synchronize()
@@ -441,7 +441,7 @@ def filter_leg(po, tree, cams, tau=0.01):
     n_samples = 0.0
     for c in cams[:20]:
         po.render_camera(tree, c, stop_T=STOP_T, aux=True, aux_out=aux)
-        n_samples += float(aux[..., po.AUX_SAMPLES].sum())
+        n_samples += float(aux[..., po.AUX_SAMPLES].double().sum())
     n_samples /= 20
     t0 = time.perf_counter()
     pruned, kept = po.visibility.prune(tree, w, tau)

@@ -162,7 +162,9 @@ po_status po_tree_validate(const po_tree_desc* desc, int64_t n_nodes, const int3
 
 /* -------------------------------------------------------------------- bind
  * Wraps device arrays (child, sigma, sh as described above) in a handle.  No
- * data is copied or checked on the device; the kernels treat an out-of-range
+ * data is copied or checked on the device (po_tree_build_index, called once
+ * after binding, adds the traversal index that speeds up the walk; without
+ * it the kernels walk the caller's child array); the kernels treat an out-of-range
  * entry, or an internal node below depth D, as empty space and count it in
  * the device error counter (po_device_errors), so a malformed array cannot
  * make them read out of bounds.  d_sh must be aligned to 4 bytes (16 for the
@@ -198,6 +200,40 @@ po_status po_tree_bind_sg(const po_tree_desc* desc, int64_t n_nodes, const int32
 po_status po_tree_bind_codebook(const po_tree_desc* desc, int64_t n_nodes, const int32_t* d_child, int64_t n_leaves,
                                 const void* d_sigma, const uint16_t* d_index, const void* d_codebook, int32_t M,
                                 po_tree** out);
+/* po_tree_build_index: builds the handle's traversal index, a derived copy
+ * of the child array that the renders, gradients and the filter walk
+ * instead of the caller's array.  The nodes above level M = D - 3 keep
+ * their child entries; each internal node of level M becomes a brick of
+ * 8 x 8 x 8 entries, one per finest cell of its cube, naming the leaf (or
+ * empty space) that holds the cell and that leaf's level.  A walk step
+ * inside one brick then needs one dependent read instead of one per level
+ * below the common ancestor; the segments, samples and results are those of
+ * the plain octree walk (Sec. 4.2, "Rendering": the exact voxel crossings).
+ * Reads the child array back to the host on `stream` (waiting for the
+ * stream), checks it as po_tree_validate does, and allocates the index on
+ * the current device (n_top * 32 + n_bricks * 2048 bytes, a few percent of
+ * the leaf records); the handle owns it until po_tree_destroy.  Trees of
+ * depth < 4 need none (PO_OK, nothing built); a second call is a no-op.  Must
+ * not run while work that uses the handle is queued or running.  Errors:
+ * PO_ERR_INVALID (NULL), PO_ERR_TREE (malformed child array: the handle is
+ * unchanged and renders walk the caller's array, counting malformed entries
+ * as device errors), PO_ERR_UNSUPPORTED (2^29 - 2 leaves or more, or an
+ * index of 4 GiB or more), PO_ERR_OOM, PO_ERR_DEVICE. */
+po_status po_tree_build_index(po_tree* t, void* stream);
+/* po_tree_index_host: host only.  The traversal index po_tree_build_index
+ * builds, from a host copy of a child array of depth D >= 4: writes *n_top
+ * (nodes above level D - 3) and *n_bricks, and, when h_index is not NULL,
+ * h_index[n_top * 8 + n_bricks * 512]: the renumbered nodes' child entries
+ * (an entry >= n_top names brick entry - n_top), then the bricks, entry
+ * slot1 * 64 + slot2 * 8 + slot3 of a brick (the child slots of the three
+ * levels below its cube) being ((leaf + 1) << 2) | (D - level) of the leaf
+ * holding that finest cell, 0 << 2 for empty space.  Call with NULL first
+ * for the sizes.  Errors: as po_tree_validate, PO_ERR_INVALID (depth < 4),
+ * PO_ERR_UNSUPPORTED (as po_tree_build_index). */
+po_status po_tree_index_host(const po_tree_desc* desc, int64_t n_nodes, const int32_t* h_child, int64_t n_leaves,
+                             int64_t* n_top, int64_t* n_bricks, int32_t* h_index);
+/* po_tree_destroy: releases the handle; if it holds a traversal index, waits
+ * for the index's device to finish its work and frees it. */
 po_status po_tree_destroy(po_tree* t);
 
 /* ------------------------------------------------------------------ render
@@ -232,6 +268,7 @@ po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, co
 po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_render_opts* opts,
                            float* d_rgb, float* d_aux, void* stream);
 
+
 /* po_camera_rays: writes the pixel-centre rays of a camera, in row-major
  * pixel order, as d_origins[H*W][3] (the camera position) and
  * d_dirs[H*W][3] (unit directions, evaluated in FP64 and rounded to float32).
@@ -256,7 +293,14 @@ po_status po_camera_rays(const po_camera* cam, float* d_origins, float* d_dirs, 
  * transmittance and colour prefix in front come from a forward pass over the
  * pieces, then every piece before the early stop is differentiated in
  * parallel (a cell cut between two pieces is two segments whose gradients add
- * up to the cell's).  Uses the work queue of po_render_camera.
+ * up to the cell's).  Uses the work queue of po_render_camera.  The pieces
+ * are cut as po_render_rays cuts the same n rays (and both run in one pass
+ * below 65536 rays or with PO_ONE_PASS), so the transmittance in front of
+ * every sample is the same float product in the render and here and the
+ * backward stops on the sample where that render stopped: d_rgb_fwd must
+ * come from a po_render_rays call with the same n and options (else, where a
+ * ray's T lands within float rounding of stop_T, the two may stop one sample
+ * apart and that ray's gradient is of the other stop point's colour).
  * Errors: PO_ERR_INVALID, PO_ERR_UNSUPPORTED (tree not PO_F32, or viewer
  * options sh_off / clip set), PO_ERR_DEVICE. */
 po_status po_render_rays_backward(const po_tree* t, int64_t n, const float* d_origins,

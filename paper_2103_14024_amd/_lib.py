@@ -67,6 +67,8 @@ _SIGS = {
     "po_tree_bind_codebook": [ctypes.POINTER(po_tree_desc), _I64, _P, _I64, _P, _P, _P, _I32, ctypes.POINTER(_P)],
     "po_codebook_build": [_I64, _I32, _P, _I64, _I32, _P, _P, _I64, _P],
     "po_tree_destroy": [_P],
+    "po_tree_build_index": [_P, _P],
+    "po_tree_index_host": [ctypes.POINTER(po_tree_desc), _I64, _P, _I64, _P, _P, _P],
     "po_render_rays": [_P, _I64, _P, _P, ctypes.POINTER(po_render_opts), _P, _P, _P],
     "po_render_camera": [_P, ctypes.POINTER(po_camera), ctypes.POINTER(po_render_opts), _P, _P, _P],
     "po_render_rays_backward": [_P, _I64, _P, _P, ctypes.POINTER(po_render_opts), _P, _P, _P, _P, _P],

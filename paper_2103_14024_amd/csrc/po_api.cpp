@@ -353,9 +353,11 @@ po_status po_builder_destroy(po_builder* b) {
     return ok();
 }
 
-po_status po_tree_validate(const po_tree_desc* desc, int64_t n_nodes, const int32_t* h_child, int64_t n_leaves,
-                           const void* h_sigma) {
-    if (po_status s = check_desc(desc)) return s;
+// po_tree_validate's checks; codebook: desc describes a codebook tree (its
+// records are index records, whose stride rules differ)
+static po_status validate_tree(const po_tree_desc* desc, int64_t n_nodes, const int32_t* h_child,
+                               int64_t n_leaves, const void* h_sigma, bool codebook) {
+    if (po_status s = check_desc(desc, codebook)) return s;
     if (n_nodes < 1 || n_nodes >= (1ll << 31) / 8) return fail(PO_ERR_INVALID, "n_nodes %lld out of range", (long long)n_nodes);
     if (n_leaves < 0 || n_leaves >= (1ll << 31) - 1) return fail(PO_ERR_INVALID, "n_leaves %lld out of range", (long long)n_leaves);
     if (!h_child) return fail(PO_ERR_INVALID, "child array is NULL");
@@ -407,6 +409,11 @@ po_status po_tree_validate(const po_tree_desc* desc, int64_t n_nodes, const int3
         }
     }
     return ok();
+}
+
+po_status po_tree_validate(const po_tree_desc* desc, int64_t n_nodes, const int32_t* h_child, int64_t n_leaves,
+                           const void* h_sigma) {
+    return validate_tree(desc, n_nodes, h_child, n_leaves, h_sigma, false);
 }
 
 po_status po_tree_leaf_cells(const po_tree_desc* desc, int64_t n_nodes, const int32_t* h_child, int64_t n_leaves,
@@ -479,6 +486,9 @@ static po_status bind_impl(const po_tree_desc* desc, int64_t n_nodes, const int3
     t->sh = d_sh;
     t->K = (desc->sh_degree + 1) * (desc->sh_degree + 1);
     t->codebook = cb;
+    t->d_index = nullptr;
+    t->index_device = -1;
+    t->n_bricks = 0;
     t->stride = desc->sh_stride ? desc->sh_stride : (cb ? (t->K + 3) / 4 * 4 : 3 * t->K);
     const size_t rb = (size_t)t->stride * es;
     t->vec_bytes = 4;
@@ -497,10 +507,12 @@ static po_status bind_impl(const po_tree_desc* desc, int64_t n_nodes, const int3
     else
         k.lobes = d_lobes;
     k.cb_entries = cb ? cb_entries : 0;
-    k.n_nodes = (int32_t)n_nodes;
+    k.n_top = (int32_t)n_nodes;
+    k.brick_level = (int16_t)desc->depth;  // no bricks until po_tree_build_index
+    k.index_bytes = (uint32_t)(n_nodes * 32);
     k.n_leaves = (int32_t)n_leaves;
     k.stride = t->stride;
-    k.depth = desc->depth;
+    k.depth = (int16_t)desc->depth;
     k.sigma_bytes = (uint32_t)(n_leaves * es);
     k.sh_bytes = (uint32_t)(n_leaves * (int64_t)t->stride * es);
     for (int a = 0; a < 3; ++a) k.lo[a] = (double)desc->center[a] - (double)desc->half_size;
@@ -528,7 +540,153 @@ po_status po_tree_bind_sg(const po_tree_desc* desc, int64_t n_nodes, const int32
     return bind_impl(desc, n_nodes, d_child, n_leaves, d_sigma, d_sh, d_lobes, nullptr, 0, out);
 }
 
+// Traversal index of a valid tree of depth D >= 4 (host copy h of its child
+// array): the nodes above level M = D - 3 renumbered in breadth-first order,
+// their entries of level-M internal nodes replaced by n_top + brick number,
+// then one 512-entry brick per internal node of level M.
+static po_status index_of(const po_tree_desc* desc, bool codebook, int64_t n, const int32_t* h, int64_t n_leaves,
+                          std::vector<int32_t>& index, int64_t& n_top, int64_t& n_bricks) {
+    if (po_status st = validate_tree(desc, n, h, n_leaves, nullptr, codebook)) return st;
+    const int D = desc->depth;
+    const int M = D - 3;
+    if (n_leaves >= (1ll << 29) - 1)
+        return fail(PO_ERR_UNSUPPORTED, "traversal index: %lld leaves exceed 2^29 - 2", (long long)n_leaves);
+    try {
+        // levels in breadth-first order from the root (the array is a valid tree)
+        std::vector<int32_t> lvl((size_t)n, -1), id((size_t)n, -1);
+        std::vector<int64_t> order;
+        order.reserve((size_t)n);
+        lvl[0] = 0;
+        order.push_back(0);
+        for (size_t q = 0; q < order.size(); ++q)
+            for (int c = 0; c < 8; ++c) {
+                const int32_t ch = h[(size_t)order[q] * 8 + c];
+                if (ch > 0) {
+                    lvl[ch] = lvl[order[q]] + 1;
+                    order.push_back(ch);
+                }
+            }
+        // nodes above level M keep their breadth-first order from 0; the
+        // internal nodes of level M become bricks in the same order
+        n_top = 0;
+        n_bricks = 0;
+        for (int64_t v : order) {
+            if (lvl[v] < M)
+                id[v] = (int32_t)n_top++;
+            else if (lvl[v] == M)
+                id[v] = (int32_t)n_bricks++;
+        }
+        const uint64_t words = (uint64_t)n_top * 8 + (uint64_t)n_bricks * 512;
+        if (words * 4 >= (1ull << 32) - 256 || n_top + n_bricks >= (1ll << 31))
+            return fail(PO_ERR_UNSUPPORTED, "traversal index of %llu bytes exceeds 4 GiB",
+                        (unsigned long long)(words * 4));
+        index.assign((size_t)words, 0);
+        // a brick entry: (leaf + 1) << 2 | (D - level) of the leaf holding the cell
+        auto enc = [](int32_t entry, int up) {
+            return (int32_t)((uint32_t)(entry < 0 ? -entry : 0) << 2 | (uint32_t)up);
+        };
+        for (int64_t v : order) {
+            if (lvl[v] < M) {
+                int32_t* out = &index[(size_t)id[v] * 8];
+                for (int c = 0; c < 8; ++c) {
+                    const int32_t ch = h[(size_t)v * 8 + c];
+                    out[c] = ch <= 0 ? ch : (lvl[ch] < M ? id[ch] : (int32_t)(n_top + id[ch]));
+                }
+            } else if (lvl[v] == M) {
+                int32_t* B = &index[(size_t)n_top * 8 + (size_t)id[v] * 512];
+                for (int s1 = 0; s1 < 8; ++s1) {
+                    const int32_t e1 = h[(size_t)v * 8 + s1];
+                    if (e1 <= 0) {
+                        for (int q = 0; q < 64; ++q) B[s1 * 64 + q] = enc(e1, 2);
+                        continue;
+                    }
+                    for (int s2 = 0; s2 < 8; ++s2) {
+                        const int32_t e2 = h[(size_t)e1 * 8 + s2];
+                        if (e2 <= 0) {
+                            for (int q = 0; q < 8; ++q) B[s1 * 64 + s2 * 8 + q] = enc(e2, 1);
+                            continue;
+                        }
+                        // children of a level D-1 node are leaves or empty (validated)
+                        for (int s3 = 0; s3 < 8; ++s3) B[s1 * 64 + s2 * 8 + s3] = enc(h[(size_t)e2 * 8 + s3], 0);
+                    }
+                }
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(PO_ERR_OOM, "traversal index: host allocation");
+    }
+    return ok();
+}
+
+po_status po_tree_index_host(const po_tree_desc* desc, int64_t n_nodes, const int32_t* h_child, int64_t n_leaves,
+                             int64_t* n_top, int64_t* n_bricks, int32_t* h_index) {
+    if (po_status s = check_desc(desc)) return s;
+    if (!n_top || !n_bricks) return fail(PO_ERR_INVALID, "n_top or n_bricks is NULL");
+    if (desc->depth < 4) return fail(PO_ERR_INVALID, "trees of depth %d < 4 have no traversal index", desc->depth);
+    std::vector<int32_t> index;
+    int64_t nt = 0, nb = 0;
+    if (po_status s = index_of(desc, false, n_nodes, h_child, n_leaves, index, nt, nb)) return s;
+    *n_top = nt;
+    *n_bricks = nb;
+    if (h_index) std::memcpy(h_index, index.data(), index.size() * sizeof(int32_t));
+    return ok();
+}
+
+po_status po_tree_build_index(po_tree* t, void* stream) {
+    if (!t) return fail(PO_ERR_INVALID, "tree is NULL");
+    const int D = t->desc.depth;
+    if (t->d_index || D < 4) return ok();  // built already, or too shallow for 8x8x8 bricks
+    const int64_t n = t->n_nodes;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_fail(e, "traversal index: current device");
+    std::vector<int32_t> h, index;
+    int64_t n_top = 0, n_bricks = 0;
+    try {
+        h.resize((size_t)n * 8);
+    } catch (const std::bad_alloc&) {
+        return fail(PO_ERR_OOM, "traversal index: host allocation");
+    }
+    e = hipMemcpyAsync(h.data(), t->child, (size_t)n * 32, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_fail(e, "traversal index: reading the child array");
+    if (po_status st = index_of(&t->desc, t->codebook, n, h.data(), t->n_leaves, index, n_top, n_bricks)) return st;
+    const size_t bytes = index.size() * sizeof(int32_t);
+    void* d = nullptr;
+    if ((e = hipMalloc(&d, bytes)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PO_ERR_OOM, "traversal index: %zu bytes of device memory", bytes);
+    }
+    e = hipMemcpyAsync(d, index.data(), bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return device_fail(e, "traversal index: upload");
+    }
+    t->d_index = d;
+    t->index_device = dev;
+    t->n_bricks = n_bricks;
+    t->kt.child = static_cast<const int32_t*>(d);
+    t->kt.n_top = (int32_t)n_top;
+    t->kt.brick_level = (int16_t)(D - 3);
+    t->kt.index_bytes = (uint32_t)bytes;
+    return ok();
+}
+
 po_status po_tree_destroy(po_tree* t) {
+    if (t && t->d_index) {
+        // the index may still be read by queued work: wait for its device
+        int cur = 0;
+        const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+        hipError_t e = hipSetDevice(t->index_device);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipFree(t->d_index);
+        if (have_cur) (void)hipSetDevice(cur);
+        delete t;
+        if (e != hipSuccess) return device_fail(e, "freeing the traversal index");
+        return ok();
+    }
     delete t;
     return ok();
 }

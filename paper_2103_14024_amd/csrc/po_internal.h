@@ -10,17 +10,27 @@
 
 // Kernel-side view of a bound tree (plain data, passed by value).
 struct KTree {
-    const int32_t* child;   // [n_nodes][8]
+    // Child entries the walk reads: the caller's child array [n_top][8], or
+    // the library's traversal index (po_tree_build_index): the nodes above
+    // brick_level, renumbered, [n_top][8], then one brick of 8x8x8 cells per
+    // internal node of level brick_level, [n_bricks][512].  An entry of a
+    // level-brick_level cell >= n_top names brick (entry - n_top).  A brick
+    // entry is ((leaf + 1) << 2) | (D - level) of the leaf holding the cell
+    // (0 << 2 for empty space), indexed by the child slots of the three levels
+    // below the brick's cube (slot1 << 6 | slot2 << 3 | slot3).
+    const int32_t* child;
     const void* sigma;      // [n_leaves] float or half
     const void* sh;         // [n_leaves][stride] float or half
     union {                 // a tree has SG lobes or a codebook, never both
         const float* lobes;     // cb_entries == 0: nullptr (SH basis) or [K][4] spherical-Gaussian lobes
         const void* codebook;   // cb_entries > 0: [K][cb_entries][4] float16 colours; sh holds uint16 indices
     };
-    int32_t n_nodes;
+    int32_t n_top;          // nodes in `child` (all of the caller's nodes when brick_level == depth)
     int32_t n_leaves;
     int32_t stride;         // elements per SH record
-    int32_t depth;          // D
+    int16_t depth;          // D
+    int16_t brick_level;    // M: cells below level M are resolved by bricks; M == D: no bricks
+    uint32_t index_bytes;   // bytes readable through `child`
     int32_t cb_entries;     // codebook entries per basis function (0: no codebook)
     uint32_t sigma_bytes;   // n_leaves * element size (< 2^32)
     uint32_t sh_bytes;      // n_leaves * stride * element size (< 2^32 - 256)
@@ -103,22 +113,16 @@ constexpr int kSplitMaxChunks = 16;
 #ifndef PO_SPLIT_UB_FRAC
 #define PO_SPLIT_UB_FRAC 0.2f
 #endif
-// piece sizes of ray-list renders of fewer than PO_RAYS_SMALL rays, and of
-// the backward
+// piece sizes of ray-list passes (render and backward) of fewer than
+// PO_RAYS_SMALL rays
 #ifndef PO_RAYS_SMALL
 #define PO_RAYS_SMALL (1 << 18)
 #endif
 #ifndef PO_RAYS_CHUNK_STEPS
-#define PO_RAYS_CHUNK_STEPS 8
+#define PO_RAYS_CHUNK_STEPS 12
 #endif
 #ifndef PO_RAYS_CHUNK_CAP
 #define PO_RAYS_CHUNK_CAP 16
-#endif
-#ifndef PO_BWD_CHUNK_STEPS
-#define PO_BWD_CHUNK_STEPS 12
-#endif
-#ifndef PO_BWD_CHUNK_CAP
-#define PO_BWD_CHUNK_CAP 16
 #endif
 struct KSplit {
     int32_t* count;        // [kSplitRegions] chunk slots claimed (may exceed the region); count2 follows
@@ -141,6 +145,17 @@ struct KSplit {
     const float* ray_d;    // ray-list renders: directions [n_rays][3]
     int64_t n_rays;
 };
+// Piece sizes of a split pass over a list of n rays.  The render and the
+// backward of the same rays cut them alike: the transmittance in front of
+// every piece is then the same float product in both, so the backward stops
+// on the sample where the render that produced its colour stopped.
+inline void po_rays_piece_sizes(int64_t n, KSplit* S) {
+    if (n < PO_RAYS_SMALL) {
+        S->chunk_steps = PO_RAYS_CHUNK_STEPS;
+        S->sub_steps = PO_RAYS_CHUNK_STEPS;
+        S->chunk_cap = PO_RAYS_CHUNK_CAP;
+    }
+}
 // Device bytes of the queues with region_slots slots per region (counters,
 // then info, head, part and viewer record of each queue).
 constexpr size_t po_split_bytes(int region_slots) {
@@ -160,6 +175,9 @@ struct po_tree {
     int32_t stride;         // elements per SH record
     int32_t vec_bytes;      // widest aligned load of a record: 16, 8 or 4
     bool codebook;          // records are codebook indices (float16 densities)
+    void* d_index;          // traversal index owned by the handle (nullptr: none built)
+    int index_device;       // device holding d_index
+    int64_t n_bricks;
     KTree kt;
 };
 

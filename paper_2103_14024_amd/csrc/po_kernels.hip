@@ -349,16 +349,32 @@ struct counts_loads : std::false_type {};
 template <class S>
 struct counts_loads<S, std::void_t<decltype(S::kCountLoads)>> : std::bool_constant<S::kCountLoads> {};
 
+// Spreads the three low bits of b to bits 0, 3 and 6.
+__device__ __forceinline__ uint32_t spread3(uint32_t b) { return (b | (b << 2) | (b << 4)) & 0x49u; }
+
+// Index of a finest cell in its 8x8x8 brick: the child slots of the three
+// levels below the brick's cube, slot1 << 6 | slot2 << 3 | slot3 (slot =
+// 4 x + 2 y + z of that level's coordinate bits).
+__device__ __forceinline__ uint32_t brick_cell(const int (&c)[3]) {
+    return (spread3((uint32_t)c[0] & 7u) << 2) | (spread3((uint32_t)c[1] & 7u) << 1) | spread3((uint32_t)c[2] & 7u);
+}
+
 template <class Sampler, bool SPLIT = false>
 __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int* __restrict__ stk,
                                      Sampler& smp) {
     const int D = tr.depth;
+    const int M = tr.brick_level;
     const int N = 1 << D;
-    const uint32_t tr_child_end = (uint32_t)tr.n_nodes * 32u;
-    const __amdgpu_buffer_rsrc_t child = raw_rsrc(tr.child, tr_child_end);
+    const uint32_t idx_end = tr.index_bytes;
+    const __amdgpu_buffer_rsrc_t child = raw_rsrc(tr.child, idx_end);
+    const uint32_t brick0 = (uint32_t)tr.n_top * 32u;  // byte offset of brick 0
     int steps = 0;
     bool pending = false, bad = false, cap_end = false;
+    // L: level of the node whose entry e is (e describes a level-(L+1) cell),
+    // or, with inb set, e is the brick entry of the cell c
     int L = 0, node = 0;
+    bool inb = false;
+    uint32_t bofs = 0;  // byte offset of the brick holding c (valid while inb)
     stk[0] = 0;
     int e = __builtin_amdgcn_raw_buffer_load_b32(child, child_slot(r.c, D, 0) << 2, 0, 0);
     if constexpr (counts_loads<Sampler>::value) smp.loads += 1;
@@ -366,33 +382,45 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
     // flight behind the entry (the compiler then waits for the entry alone)
     smp.issue(-1, 0.0f, 0.0f);
     while (true) {
-        // finish the descent: e is the entry of the level-(L+1) cell holding c
-        ++L;
-        bool malformed = (e > 0) & ((L >= D) | (e >= tr.n_nodes));
-        bad |= malformed;
-        e = malformed ? 0 : e;
-        if (e > 0) {
+        // finish the descent to the leaf holding c: its number (-1: empty) and level
+        int leaf, lvl;
+        if (inb) {
+            lvl = D - (e & 3);
+            leaf = (int)((uint32_t)e >> 2) - 1;
+        } else {
+            ++L;  // e is the entry of the level-L cell holding c
             // further levels (each waits for its own load, and for any older one)
-            while (true) {
+            while ((e > 0) & (e < tr.n_top) & (L < M)) {
                 node = e;
                 stk[L * kBlock] = node;
                 e = __builtin_amdgcn_raw_buffer_load_b32(
                     child, ((uint32_t)node << 5) | (child_slot(r.c, D, L) << 2), 0, 0);
                 if constexpr (counts_loads<Sampler>::value) smp.loads += 1;
                 ++L;
-                malformed = (e > 0) & ((L >= D) | (e >= tr.n_nodes));
+            }
+            if ((e > 0) & (L == M) & (M < D) & (e >= tr.n_top)) {
+                // the level-M cube holding c is a brick: one load gives the leaf
+                bofs = brick0 + (uint32_t)(e - tr.n_top) * 2048u;
+                e = __builtin_amdgcn_raw_buffer_load_b32(child, bofs + (brick_cell(r.c) << 2), 0, 0);
+                if constexpr (counts_loads<Sampler>::value) smp.loads += 1;
+                inb = true;
+                lvl = D - (e & 3);
+                leaf = (int)((uint32_t)e >> 2) - 1;
+            } else {
+                // a leaf or empty cube of level L; any other positive entry
+                // (past the nodes, or internal at the deepest level) is malformed
+                const bool malformed = e > 0;
                 bad |= malformed;
-                e = malformed ? 0 : e;
-                if (e <= 0) break;
+                leaf = malformed ? -1 : -1 - e;
+                lvl = L;
             }
         }
-        int leaf = -1 - e;
         if (leaf >= tr.n_leaves) {
             bad = true;
             leaf = -1;
         }
         // exit parameter: the nearest far face (branch-free; pos = moving up the axis)
-        const int csz = 1 << (D - L);
+        const int csz = 1 << (D - lvl);
         int lo[3];
         bool pos[3];
         double sk[3];
@@ -405,7 +433,24 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
         double se = fmax(fmin(fmin(sk[0], sk[1]), sk[2]), r.s);
         bool cpl = true;
         if constexpr (Sampler::kClip) {
-            cpl = se <= r.s_end;
+            if constexpr (is_chunk<Sampler>::value) {
+                // a piece's cell is cut when the next piece starts inside it;
+                // that piece finds its first cell from the point at s_end as
+                // ray_setup does, so the two agree on every cell (a cell
+                // ending at s_end up to rounding is complete here exactly
+                // when the next piece starts in a later cell)
+                if (se > r.s_end) {
+                    bool inside = true;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const double q = fmin(fmax(floor(fma(r.s_end, r.dg[k], r.og[k])), 0.0), (double)(N - 1));
+                        inside &= (q >= (double)lo[k]) & (q < (double)(lo[k] + csz));
+                    }
+                    cpl = !inside;
+                }
+            } else {
+                cpl = se <= r.s_end;
+            }
             se = fmin(se, r.s_end);
         }
         const float delta = (float)((se - r.s) * r.len);
@@ -431,19 +476,27 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
         const bool capped = !out & (steps >= max_steps);
         if constexpr (!SPLIT) bad |= capped;
         const bool last = out | capped;
-        // prefetch the next cell's entry, from the deepest common ancestor: the
-        // cells agree on the coordinate bits above the highest differing one.
-        // The load is issued on every path (out of range after the last step)
-        // so the compiler can count the loads in flight exactly.
-        uint32_t pf = tr_child_end;
+        // prefetch the next cell's entry.  The cells agree on the coordinate
+        // bits above the highest differing one: inside the same brick the
+        // brick entry is read directly, else the walk restarts below the
+        // deepest common ancestor above the brick level (from the stack).
+        // The load is issued on every path (out of range after the last
+        // step) so the compiler can count the loads in flight exactly.
+        uint32_t pf = idx_end;
         if (!last) {
             const int diff = (r.c[0] ^ nc[0]) | (r.c[1] ^ nc[1]) | (r.c[2] ^ nc[2]);
-            L = D - 32 + __clz(diff);
-            node = stk[L * kBlock];
+            const int la = D - 32 + __clz(diff);
             r.c[0] = nc[0];
             r.c[1] = nc[1];
             r.c[2] = nc[2];
-            pf = ((uint32_t)node << 5) | (child_slot(r.c, D, L) << 2);
+            if (inb & (la >= M)) {
+                pf = bofs + (brick_cell(r.c) << 2);
+            } else {
+                inb = false;
+                L = la;
+                node = stk[L * kBlock];
+                pf = ((uint32_t)node << 5) | (child_slot(r.c, D, L) << 2);
+            }
         }
         if constexpr (SPLIT) {
             if (capped) {
@@ -465,7 +518,13 @@ __device__ __forceinline__ int march(const KTree& tr, Ray& r, int max_steps, int
         // walk ends only at the bottom of the body, so every path back to the
         // top has issued the same loads.
         const bool take = !stop & (leaf >= 0) & (delta > 0.0f);
-        if constexpr (is_chunk<Sampler>::value) smp.cpl_next = cpl;
+        if constexpr (is_chunk<Sampler>::value) {
+            smp.cpl_next = cpl;
+            // a piece's first cell without a sample (the zero-length rest of
+            // a cell the previous piece cut, or a start on a face) still
+            // carries the stop test at its end
+            if ((steps == 1) & !take & !stop) stop = smp.test_first(cpl);
+        }
         smp.issue(take ? leaf : -1, delta, t_in);
         pending = take;
         if constexpr (SPLIT) cap_end = capped & !stop;
@@ -600,8 +659,9 @@ struct CbSampler {
 // compositing is associative, chunk results combine front to back with the
 // over operator.  Early stopping is tested where the sequential walk tests it,
 // at the end of a cell: a sample whose cell continues past s_hi (cut by the
-// chunk boundary) is composited without a test, and its remainder, the first
-// sample of the next chunk, carries the test.  Tlast is T after the last
+// chunk boundary: the next chunk starts inside it) is composited without a
+// test, and its remainder, the first cell of the next chunk, carries the
+// test, also when it has zero length and takes no sample.  Tlast is T after the last
 // tested sample (-1: none); the chunk stops itself once T < stopT there,
 // since its walk cannot matter past that point for any transmittance in
 // front of it.
@@ -629,6 +689,15 @@ struct ChunkOf : Base {
         if constexpr (COUNT) smp_cut = !cpl;
         if (!cpl) return false;
         Tlast = this->Tl;
+        hit |= st;
+        return st;
+    }
+    // the stop test at the end of a first cell that took no sample (c: the
+    // cell ends inside the piece)
+    __device__ __forceinline__ bool test_first(bool c) {
+        if (!c) return false;
+        Tlast = this->Tl;
+        const bool st = this->Tl < this->stopT;
         hit |= st;
         return st;
     }
@@ -2044,11 +2113,8 @@ hipError_t backward_split_t(const po_tree* t, int64_t n, const float* o, const f
         g3(2u * g2.x), blk(kBlock);
     const size_t lds = stack_bytes(t->kt.depth);
     const bool sg = t->kt.lobes != nullptr;
-    // smaller pieces than the forward's: a backward step costs more (the
-    // gradient atomics), and a batch of rays fills the chip less than a frame
-    S.chunk_steps = PO_BWD_CHUNK_STEPS;
-    S.sub_steps = PO_BWD_CHUNK_STEPS;
-    S.chunk_cap = PO_BWD_CHUNK_CAP;
+    // the pieces of the render of the same rays
+    po_rays_piece_sizes(n, &S);
 #define PO_BSPLIT(VEC_, NL_)                                                                                    \
     do {                                                                                                       \
         hipLaunchKernelGGL((k_backward_split<K, VEC_, NL_>), g1, blk, lds, s, B, S, rgb_fwd, grad, gsig, gsh); \
@@ -2234,11 +2300,7 @@ hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, con
     // a batch of rays below a frame's size fills the chip less: smaller pieces
     // (65536 random rays of the depth-8 training tree: 203 us with 8-cell
     // pieces, 325 us with the frame's 32, 300 us in one pass)
-    if (n < PO_RAYS_SMALL) {
-        S.chunk_steps = PO_RAYS_CHUNK_STEPS;
-        S.sub_steps = PO_RAYS_CHUNK_STEPS;
-        S.chunk_cap = PO_RAYS_CHUNK_CAP;
-    }
+    po_rays_piece_sizes(n, &S);
     const int n_blocks = (int)((n + kBlock - 1) / kBlock);
     const int variant = po_fwd_variant(op, aux, t->kt);
     return t->desc.dtype == PO_F32 ? po_rays_split_f32(t, job, n_blocks, variant, S, s)

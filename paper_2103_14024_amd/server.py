@@ -6,7 +6,8 @@ least `split_tiles` 16x16 tiles is rendered whole by one job, which the
 library renders in pieces (long walks cut and walked in parallel); smaller
 requests are cut into chunks of tiles, and chunks of several requests -- of
 any scene and resolution -- are packed into batched launches
-(po_render_batch, up to 16 jobs each).  Launches go round-robin to a few HIP
+(po_render_batch, up to 16 jobs each), each ray of a chunk walked by one
+lane (one pass).  Launches go round-robin to a few HIP
 streams, so a large frame and the batches of small ones run on the device
 together.  Requests that arrive while others are in flight join the next
 launch.  A request is complete when the last launch holding one of its tiles
@@ -217,8 +218,10 @@ class Server:
                     n = min(share, req.tiles - req.next_tile, budget)
                     if n <= 0 or len(jobs) == L.PO_BATCH_MAX_JOBS:
                         break
+                    # batched chunks walk each ray in one lane (one_pass), so a
+                    # request's pixels do not depend on how it was cut or batched
                     jobs.append(Job(self.trees[req.scene], req.cam, self.arena.view(req), req.next_tile,
-                                    req.next_tile + n, self.bg, self.stop_T))
+                                    req.next_tile + n, self.bg, self.stop_T, one_pass=True))
                     parts.append((req, n))
                     req.next_tile += n
                     budget -= n

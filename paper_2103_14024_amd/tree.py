@@ -98,7 +98,7 @@ class Tree:
     handle.  The handle borrows the tensors; this object keeps them alive."""
 
     def __init__(self, depth, sh_degree, child, sigma, sh, center=(0.0, 0.0, 0.0), half=1.0, perm=None,
-                 lobes=None, codebook=None):
+                 lobes=None, codebook=None, index=True):
         import torch
 
         self.depth, self.sh_degree = int(depth), int(sh_degree)
@@ -150,6 +150,11 @@ class Tree:
             L.call("po_tree_bind_sg", ctypes.byref(self.desc), int(child.shape[0]), child.data_ptr(),
                    self.n_leaves, *leaf_ptrs, lobes.data_ptr(), ctypes.byref(h))
         self._h = h
+        # the traversal index (8x8x8 bricks below level depth - 3; trees of
+        # depth < 4 have none): renders walk it instead of `child`
+        self.indexed = bool(index) and self.depth >= 4
+        if self.indexed:
+            L.call("po_tree_build_index", h, ctypes.c_void_p(torch.cuda.current_stream(child.device).cuda_stream))
 
     @property
     def handle(self) -> ctypes.c_void_p:
@@ -171,7 +176,7 @@ class Tree:
 
     @classmethod
     def from_cells(cls, depth, sh_degree, cells, sigma, sh, center=(0.0, 0.0, 0.0), half=1.0, dtype="f32",
-                   device="cuda", stride=None, lobes=None):
+                   device="cuda", stride=None, lobes=None, index=True):
         """Builds the tree on the host from leaf cells (level, i, j, k) with
         values in the caller's order, reorders the values into leaf order and
         uploads everything to `device`.  lobes: None (SH colour basis) or
@@ -199,17 +204,17 @@ class Tree:
         t_lobes = None
         if lobes is not None:
             t_lobes = torch.from_numpy(np.ascontiguousarray(np.asarray(lobes, np.float32).reshape(K, 4))).to(dev)
-        return cls(depth, sh_degree, t_child, t_sig, t_sh, center, half, perm=perm, lobes=t_lobes)
+        return cls(depth, sh_degree, t_child, t_sig, t_sh, center, half, perm=perm, lobes=t_lobes, index=index)
 
     @classmethod
-    def from_scene(cls, scene: dict, dtype="f32", device="cuda", stride=None):
+    def from_scene(cls, scene: dict, dtype="f32", device="cuda", stride=None, index=True):
         return cls.from_cells(scene["depth"], scene["sh_degree"], scene["cells"], scene["sigma"], scene["sh"],
                               scene["center"], scene["half"], dtype=dtype, device=device, stride=stride,
-                              lobes=scene.get("lobes"))
+                              lobes=scene.get("lobes"), index=index)
 
     @classmethod
     def from_cells_codebook(cls, depth, sh_degree, cells, sigma, sh, M=65536, center=(0.0, 0.0, 0.0), half=1.0,
-                            device="cuda", index_stride=None):
+                            device="cuda", index_stride=None, index=True):
         """Codebook tree (App. B.2): the coefficients are median-cut per basis
         function in the caller's cell order (po_codebook_build), the densities
         kept as float16; records hold 16-bit codebook positions."""
@@ -228,7 +233,7 @@ class Tree:
         t_sig = torch.from_numpy(np.ascontiguousarray(sig[perm].astype(np.float16))).to(dev)
         t_idx = torch.from_numpy(np.ascontiguousarray(idx[perm]).view(np.int16)).to(dev)
         t_cb = torch.from_numpy(cb.view(np.float16)).to(dev)
-        return cls(depth, sh_degree, t_child, t_sig, t_idx, center, half, perm=perm, codebook=t_cb)
+        return cls(depth, sh_degree, t_child, t_sig, t_idx, center, half, perm=perm, codebook=t_cb, index=index)
 
     def leaf_values(self):
         """(sigma (n,), sh (n, 3, K)) as float32 NumPy arrays in the caller's cell

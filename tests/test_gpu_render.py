@@ -192,7 +192,7 @@ def test_device_error_counter(po):
 
     _announce("device error counter")
     s = scenes.scene_small()
-    tree = po.Tree.from_scene(s)
+    tree = po.Tree.from_scene(s, index=False)  # the kernels walk the caller's array
     o, d = _ray_set(500)
     po.reset_device_errors()
     po.render_rays(tree, _dev(o), _dev(d), max_steps=2)
@@ -201,7 +201,7 @@ def test_device_error_counter(po):
     po.reset_device_errors()
     child = tree.child.clone()
     child[child > 0] = child.shape[0] + 100     # every internal reference out of range
-    bad = po.Tree(s["depth"], s["sh_degree"], child, tree.sigma, tree.sh)
+    bad = po.Tree(s["depth"], s["sh_degree"], child, tree.sigma, tree.sh, index=False)
     rgb = po.render_rays(bad, _dev(o), _dev(d), bg=(0.5, 0.5, 0.5)).cpu().numpy()
     assert po.device_errors() > 0
     assert np.isfinite(rgb).all()

@@ -48,16 +48,27 @@ def test_alone_equals_mix(po, split_tiles):
         assert st.whole == sum(1 for r in reqs if r.cam.n_tiles >= split_tiles) > 0
     import torch
 
+    worst = 0.0
     for r in reqs:
         # the request rendered alone by one job of the whole image, in one pass
         # or in pieces as in the mix
         whole = split_tiles is not None and r.cam.n_tiles >= split_tiles
         alone = torch.empty((r.cam.height, r.cam.width, 3), device="cuda")
         po.render_batch([po.Job(trees[r.scene], r.cam, alone, one_pass=not whole)])
-        # bit for bit: a batched job walks each ray in one lane; a whole
-        # request's pieces depend on its rays only
-        assert np.array_equal(alone.cpu().numpy(), r.image), r.rid
+        a = alone.cpu().numpy()
+        if not whole:
+            # bit for bit: a batched job walks each ray in one lane
+            assert np.array_equal(a, r.image), r.rid
+        else:
+            # in pieces, a walk whose region of the work queue is full is
+            # finished by its own lane instead (which waves find a region full
+            # depends on timing): the same samples, summed in another order
+            d = float(np.abs(a - r.image).max())
+            worst = max(worst, d)
+            assert d <= 1.1e-4, (r.rid, d)
         if r.cam.width * r.cam.height >= 1 << 16:
             ref = po.render_camera(trees[r.scene], r.cam).cpu().numpy()
-            assert np.abs(ref - r.image).max() <= (0.0 if whole else 1.1e-4), r.rid
+            assert np.abs(ref - r.image).max() <= 1.1e-4, r.rid
         assert r.t_done >= r.arrival
+    if split_tiles is not None:
+        print(f"[gpu] whole requests, alone vs mix: max difference {worst:.2e}", file=sys.stderr, flush=True)

@@ -367,13 +367,17 @@ def test_split_backward(po, fog, scene, gamma):
     g = np.random.default_rng(47).standard_normal((len(o), 3)).astype(np.float32)
     bg = (0.9, 0.4, 0.1)
     og, dg, gg = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (o, d, g))
+    # each backward differentiates the colour of the render that cuts the rays
+    # alike (the same float transmittances, so the same early stop): the
+    # split render for the split backward, the one-pass render for the halves
     rgb = po.render_rays(tree, og, dg, bg=bg, stop_T=gamma)
+    rgb1 = po.render_rays(tree, og, dg, bg=bg, stop_T=gamma, one_pass=True)
     gs, gsh = po.render_rays_backward(tree, og, dg, rgb, gg, bg=bg, stop_T=gamma)
     h = len(o) // 2
     hs = torch.zeros_like(gs)
     hsh = torch.zeros_like(gsh)
     for a, b in ((0, h), (h, len(o))):
-        po.render_rays_backward(tree, og[a:b], dg[a:b], rgb[a:b], gg[a:b], bg=bg, stop_T=gamma, grad_sigma=hs,
+        po.render_rays_backward(tree, og[a:b], dg[a:b], rgb1[a:b], gg[a:b], bg=bg, stop_T=gamma, grad_sigma=hs,
                                 grad_sh=hsh)
     torch.cuda.synchronize()
     (ls, hs_), (lh, hh), n_str = gradcheck.grad_envelope(ot, o, d, g, bg, gamma)
