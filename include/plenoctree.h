@@ -268,6 +268,26 @@ po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, co
 po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_render_opts* opts,
                            float* d_rgb, float* d_aux, void* stream);
 
+/* po_render_camera_noalloc: po_render_camera for callers that cannot
+ * allocate device memory -- code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  It takes the same arguments,
+ * writes the same outputs and returns the same errors, but calls no
+ * hipMalloc, hipFree or allocating library routine: its work queue is a
+ * fixed array of 100,663,808 bytes that the library holds in a static
+ * device variable, one copy on each GPU it runs on, kept until the
+ * process ends.  Its device address is looked up on the first call on a
+ * device.  The queue holds 64 regions of 8192 pieces (a quarter of the
+ * per-stream queue); a long walk that finds its region full is finished by
+ * its own lane, which changes the speed, not the result beyond float
+ * rounding.  Images of more than 2^22 pixels (4,194,304; e.g. 2048 x 2048)
+ * are rejected with PO_ERR_INVALID before any work is queued: render those
+ * with po_render_camera.
+ * Every call on one GPU shares that GPU's array, whatever the stream, and
+ * the array keeps the last call's contents (each call clears the counters
+ * it needs): calls that overlap on one GPU race, so the caller orders them
+ * (one stream, or events).  Calls on different GPUs are independent. */
+po_status po_render_camera_noalloc(const po_tree* t, const po_camera* cam, const po_render_opts* opts,
+                                   float* d_rgb, float* d_aux, void* stream);
 
 /* po_camera_rays: writes the pixel-centre rays of a camera, in row-major
  * pixel order, as d_origins[H*W][3] (the camera position) and

@@ -71,6 +71,7 @@ _SIGS = {
     "po_tree_index_host": [ctypes.POINTER(po_tree_desc), _I64, _P, _I64, _P, _P, _P],
     "po_render_rays": [_P, _I64, _P, _P, ctypes.POINTER(po_render_opts), _P, _P, _P],
     "po_render_camera": [_P, ctypes.POINTER(po_camera), ctypes.POINTER(po_render_opts), _P, _P, _P],
+    "po_render_camera_noalloc": [_P, ctypes.POINTER(po_camera), ctypes.POINTER(po_render_opts), _P, _P, _P],
     "po_render_rays_backward": [_P, _I64, _P, _P, ctypes.POINTER(po_render_opts), _P, _P, _P, _P, _P],
     "po_render_batch": [_I32, ctypes.POINTER(po_job), _P],
     "po_camera_tiles": [ctypes.POINTER(po_camera), ctypes.POINTER(_I32)],

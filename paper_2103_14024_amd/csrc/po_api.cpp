@@ -717,11 +717,18 @@ po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, co
     return ok();
 }
 
-po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_render_opts* opts, float* d_rgb,
-                           float* d_aux, void* stream) {
+// po_render_camera and po_render_camera_noalloc: the same render, with the
+// per-stream queue (allocated on first use) or the fixed per-device one.
+static po_status render_camera_impl(const po_tree* t, const po_camera* cam, const po_render_opts* opts,
+                                    float* d_rgb, float* d_aux, void* stream, bool noalloc) {
     if (!t) return fail(PO_ERR_INVALID, "tree is NULL");
     if (po_status s = check_camera(cam)) return s;
     if (po_status s = check_opts(opts)) return s;
+    if (noalloc && (int64_t)cam->width * cam->height > kNoAllocMaxPixels)
+        return fail(PO_ERR_INVALID,
+                    "po_render_camera_noalloc: %d x %d = %lld pixels exceeds the %lld its fixed queue is sized for; "
+                    "use po_render_camera",
+                    cam->width, cam->height, (long long)cam->width * cam->height, (long long)kNoAllocMaxPixels);
     if (!d_rgb) return fail(PO_ERR_INVALID, "output image is NULL");
     if ((opts->flags & PO_OUT_AUX) && !d_aux) return fail(PO_ERR_INVALID, "PO_OUT_AUX set but aux is NULL");
     KJob j;
@@ -739,13 +746,28 @@ po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_rend
     const int variant = po_fwd_variant(j.op, j.aux, t->kt);
     KSplit S;
     hipError_t e;
-    if (!(j.op.flags & PO_ONE_PASS) && (int64_t)cam->width * cam->height >= kSplitMinPixels &&
-        j.op.max_steps > PO_SPLIT_STEPS && split_queue(stream, &S))
+    const bool split = !(j.op.flags & PO_ONE_PASS) && (int64_t)cam->width * cam->height >= kSplitMinPixels &&
+                       j.op.max_steps > PO_SPLIT_STEPS;
+    if (split && noalloc) {
+        if ((e = po_noalloc_queue(&S)) != hipSuccess) return device_fail(e, "locating the fixed work queue");
         e = po_launch_camera_split(t, j, 4 * tiles_of(cam), variant, S, (hipStream_t)stream);
-    else
+    } else if (split && split_queue(stream, &S)) {
+        e = po_launch_camera_split(t, j, 4 * tiles_of(cam), variant, S, (hipStream_t)stream);
+    } else {
         e = po_launch_camera_jobs(t, 1, &j, 4 * tiles_of(cam), variant, (hipStream_t)stream);
+    }
     if (e != hipSuccess) return device_fail(e, "render_camera launch");
     return ok();
+}
+
+po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_render_opts* opts, float* d_rgb,
+                           float* d_aux, void* stream) {
+    return render_camera_impl(t, cam, opts, d_rgb, d_aux, stream, false);
+}
+
+po_status po_render_camera_noalloc(const po_tree* t, const po_camera* cam, const po_render_opts* opts,
+                                   float* d_rgb, float* d_aux, void* stream) {
+    return render_camera_impl(t, cam, opts, d_rgb, d_aux, stream, true);
 }
 
 po_status po_render_rays_backward(const po_tree* t, int64_t n, const float* d_origins, const float* d_dirs,

@@ -96,7 +96,7 @@ struct KJob {
 #endif
 constexpr int kSplitRegions = 64;
 constexpr int kSplitRegionSlots = PO_SPLIT_REGION_SLOTS;
-constexpr int kNoAllocRegionSlots = 4096;
+constexpr int kNoAllocRegionSlots = 8192;
 constexpr int kSplitMaxChunks = 16;
 #ifndef PO_SPLIT_STEPS
 #define PO_SPLIT_STEPS 32
@@ -164,6 +164,14 @@ constexpr size_t po_split_bytes(int region_slots) {
 // Points S at queues laid out in `base` (po_split_bytes(region_slots) bytes)
 // and sets the default piece sizes.
 void po_split_layout(void* base, int region_slots, KSplit* S);
+// Bytes of the fixed queue of po_render_camera_noalloc (one copy per device,
+// a static device array of the library: about 100 MB).
+constexpr size_t kNoAllocBytes = po_split_bytes(kNoAllocRegionSlots);
+// Images the fixed queue is sized for: larger ones are rejected.
+constexpr int64_t kNoAllocMaxPixels = int64_t(1) << 22;
+// Points S at the fixed queue of the current device (its device address is
+// looked up once per device, under a lock); allocates nothing.
+hipError_t po_noalloc_queue(KSplit* S);
 
 struct po_tree {
     po_tree_desc desc;

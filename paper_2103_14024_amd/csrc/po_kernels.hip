@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "po_internal.h"
@@ -43,6 +44,11 @@ __device__ unsigned long long g_po_errors = 0;
 #if PO_PART == 0
 // sums of po_traversal_stats: rays, samples, cells, child-entry loads
 __device__ unsigned long long g_po_stats[4];
+// Work queue of po_render_camera_noalloc: a file-scope device array (one
+// copy per GPU the library runs on, held until the process ends).  Host code
+// never passes this name to a kernel: it is a host-side stand-in there, and
+// po_noalloc_queue looks up each device's own address of the array.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 #endif
 
 // One wave64 per workgroup: rays finish unevenly, and single-wave workgroups
@@ -2404,6 +2410,34 @@ hipError_t po_reset_device_errors() {
         po_part_errors_4, po_part_errors_5, po_part_errors_6, po_part_errors_7};
     for (int i = 0; i < PO_PARTS; ++i)
         if ((e = part[i](nullptr, true)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocDevices];  // device address of `scratch`, per device (nullptr: not looked up yet)
+}  // namespace
+
+hipError_t po_noalloc_queue(KSplit* S) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNoAllocDevices) return hipErrorInvalidDevice;
+    void* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        if (!g_noalloc_ptr[dev]) {
+            // first call on this device, which is current: its copy of the array
+            e = hipGetSymbolAddress(&g_noalloc_ptr[dev], HIP_SYMBOL(scratch));
+            if (e != hipSuccess) {
+                g_noalloc_ptr[dev] = nullptr;
+                return e;
+            }
+        }
+        ptr = g_noalloc_ptr[dev];
+    }
+    po_split_layout(ptr, kNoAllocRegionSlots, S);
     return hipSuccess;
 }
 

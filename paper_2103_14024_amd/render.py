@@ -128,6 +128,26 @@ def render_camera(tree, cam: Camera, bg=(1.0, 1.0, 1.0), stop_T=1e-4, aux=False,
     return (img, a) if aux else img
 
 
+def render_camera_noalloc(tree, cam: Camera, out, aux_out=None, bg=(1.0, 1.0, 1.0), stop_T=1e-4, max_steps=0,
+                          stream=None, sh_off=0, clip=None, one_pass=False):
+    """render_camera through po_render_camera_noalloc, for callers that cannot
+    allocate device memory: the library allocates nothing (its work queue is
+    a fixed per-device array), and the caller passes the image `out`
+    (H, W, 3) and, for the aux columns, `aux_out` (H, W, 4).  Calls on one
+    GPU share that queue and must not overlap.  Images of more than 2^22
+    pixels are rejected."""
+    shape = (cam.height, cam.width, 3)
+    img = _out(out, shape, "out")
+    a = None
+    if aux_out is not None:
+        a = _out(aux_out, (cam.height, cam.width, AUX_WIDTH), "aux_out")
+    opts = make_opts(bg, stop_T, max_steps, a is not None, sh_off, clip, one_pass)
+    c = cam.to_c()
+    L.call("po_render_camera_noalloc", tree.handle, ctypes.byref(c), ctypes.byref(opts), img.data_ptr(),
+           a.data_ptr() if a is not None else None, _stream_ptr(stream))
+    return (img, a) if a is not None else img
+
+
 def camera_rays(cam: Camera, stream=None, device="cuda"):
     """(origins, unit dirs) of a camera's pixel-centre rays, (H*W, 3) float32 each."""
     torch = _torch()
