@@ -39,6 +39,7 @@ STOP_T = 1e-4
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "render_camera_depth9_800x800_hbm_traffic.md")
+TRAIN_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "train_step_depth8_65536rays_hbm_traffic.md")
 KERNEL_SRC = [os.path.join(ROOT, "paper_2103_14024_amd", "csrc", f) for f in ("po_kernels.hip", "po_internal.h")]
 
 
@@ -54,13 +55,14 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(dtype: str):
+def counter_traffic(dtype: str, profile: str = TRAFFIC_PROFILE, key: str = "hbm_bytes_per_frame_"):
     """HBM bytes per frame of the float32/float16 render pass (its five
-    launches) from the committed rocprofv3 counter summary (FETCH_SIZE and
-    WRITE_SIZE, scaled by a plain copy), or None when the kernel source
-    changed since."""
+    launches), or with key "hbm_bytes_per_step_" and dtype "train" per
+    optimisation step, from a committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when the
+    kernel source changed since."""
     try:
-        with open(TRAFFIC_PROFILE) as f:
+        with open(profile) as f:
             text = f.read()
     except OSError:
         return None
@@ -69,8 +71,8 @@ def counter_traffic(dtype: str):
     h = re.search(r"kernel_source_sha256_16 = `([0-9a-f]+)`", text)
     if h is None or h.group(1) != kernel_hash():
         return None
-    vals = dict(re.findall(r"(hbm_bytes_per_frame_f(?:16|32)) = `(\d+)`", text))
-    v = vals.get("hbm_bytes_per_frame_" + dtype)
+    vals = dict(re.findall(r"(hbm_bytes_per_\w+) = `(\d+)`", text))
+    v = vals.get(key + dtype)
     return float(v) if v else None
 
 
@@ -232,7 +234,7 @@ def cpu_baseline(scene, poses, frames32, frames16, budget_s=12.0, min_frames=5):
     return base, err
 
 
-def train_leg(po, scenes, steps=100, warmup=5, fit_steps=300, lr=1e7, batch=65536):
+def train_leg(po, scenes, steps=100, warmup=5, fit_steps=300, lr=1e7, batch=65536, psnr=True):
     """Differentiation workload: depth-8 blob tree (SH degree 2, float32),
     targets = 100 renders of 400x400 from the ground-truth tree, training
     from a copy perturbed by N(0, 0.3^2), SGD on random batches of 65536
@@ -258,7 +260,7 @@ def train_leg(po, scenes, steps=100, warmup=5, fit_steps=300, lr=1e7, batch=6553
     del tgt
     sig, sh = scenes.perturb(gt["sigma"], gt["sh"], 0.3, 7)
     tree = po.Tree.from_cells(gt["depth"], gt["sh_degree"], gt["cells"], sig, sh)
-    m0 = po.optim.dataset_mse(tree, o, d, t)
+    m0 = po.optim.dataset_mse(tree, o, d, t) if psnr else float("nan")
     tr = po.Trainer(tree, o, d, t, lr_sigma=lr, lr_sh=lr, batch=batch, seed=1)
     st = {"samples": 0, "node_loads": 0, "cells": 0}
     warmup = max(1, warmup)
@@ -277,7 +279,7 @@ def train_leg(po, scenes, steps=100, warmup=5, fit_steps=300, lr=1e7, batch=6553
     ms = e0.elapsed_time(e1) / steps
     for _ in range(max(0, fit_steps - steps - warmup)):
         tr.step()
-    m1 = po.optim.dataset_mse(tree, o, d, t)
+    m1 = po.optim.dataset_mse(tree, o, d, t) if psnr else float("nan")
     K = tree.K
     rec = 4 * (1 + 3 * K)
     walk = st["samples"] * rec + st["node_loads"] * 4
@@ -286,16 +288,20 @@ def train_leg(po, scenes, steps=100, warmup=5, fit_steps=300, lr=1e7, batch=6553
              "sgd": tree.n_leaves * (1 + tree.stride) * 16}
     alg = sum(parts.values())
     gbps = alg / (ms * 1e-3) / 1e9
+    tb = counter_traffic("train", TRAIN_TRAFFIC_PROFILE, "hbm_bytes_per_step_")
     return {"workload": "depth-8 blob band (%d leaves), SH degree 2, fp32, 100x400x400 targets, batch %d, "
                         "SGD lr %g" % (len(gt["cells"]), batch, lr),
             "ms_per_step": round(ms, 4), "mrays_per_s": round(batch / ms / 1e3, 2),
             "samples_per_ray": round(st["samples"] / batch, 3), "cells_per_ray": round(st["cells"] / batch, 2),
             "child_entry_reads_per_ray": round(st["node_loads"] / batch, 2),
             "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                         "frac": round(gbps / HBM_PEAK_GBPS, 4), "alg_bytes_per_step": int(alg),
+                         "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                         "traffic": None if tb is None else round(tb / (ms * 1e-3) / 1e9, 1),
+                         "hbm_bytes_per_step": None if tb is None else int(tb), "alg_bytes_per_step": int(alg),
                          "alg_bytes_per_step_parts": {k: int(v) for k, v in parts.items()},
                          "atomics_per_step": int(st["samples"] * (1 + 3 * K))},
-            "psnr_start": round(po.psnr(m0), 2), "psnr_after": round(po.psnr(m1), 2), "steps_fitted": fit_steps,
+            "psnr_start": round(po.psnr(m0), 2) if psnr else None, "psnr_after": round(po.psnr(m1), 2) if psnr else None,
+            "steps_fitted": fit_steps,
             "paper_context": "about 3M rays/s on a Tesla V100 (NeRF-synthetic)"}
 
 
@@ -504,7 +510,9 @@ def main():
     if args.calib_copy_mib:
         calib_copy(args.calib_copy_mib)
     if args.train_only:
-        print(json.dumps(train_leg(po, scenes, steps=args.steps, warmup=args.warmup, fit_steps=0)), flush=True)
+        # no dataset PSNR passes: the profile then holds the training steps
+        print(json.dumps(train_leg(po, scenes, steps=args.steps, warmup=args.warmup, fit_steps=0, psnr=False)),
+              flush=True)
         return
     t0 = time.perf_counter()
     scene = scenes.scene_blobs()
