@@ -99,10 +99,10 @@ constexpr int kSplitRegionSlots = PO_SPLIT_REGION_SLOTS;
 constexpr int kNoAllocRegionSlots = 8192;
 constexpr int kSplitMaxChunks = 16;
 #ifndef PO_SPLIT_STEPS
-#define PO_SPLIT_STEPS 32
+#define PO_SPLIT_STEPS 24
 #endif
 #ifndef PO_CHUNK_STEPS
-#define PO_CHUNK_STEPS 32
+#define PO_CHUNK_STEPS 24
 #endif
 #ifndef PO_SUB_STEPS
 #define PO_SUB_STEPS 12

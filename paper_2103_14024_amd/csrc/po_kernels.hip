@@ -1190,12 +1190,18 @@ __device__ __forceinline__ int split_slot(const int32_t* count, int region_slots
     return local < n ? region * region_slots + local : -1;
 }
 
-// The chunk and sub-chunk walks are held to 128 VGPRs (4 waves per SIMD;
-// unconstrained the chunk kernel takes 131 and 3 waves): 0.639 against
-// 0.671 ms per depth-9 800x800 frame.
+// The plain (SH, SG) chunk and sub-chunk walks of records up to 192 bytes
+// are held to 128 VGPRs (4 waves per SIMD; unconstrained the float32 K=16
+// chunk kernel takes 131 and 3 waves): 0.639 against 0.671 ms per depth-9
+// 800x800 frame.  Larger records and the viewer and codebook variants would
+// spill (K=25 float32: 180 bytes of scratch, half the frame rate), so they
+// keep their natural count.
+template <typename T, int K, int V>
+constexpr int kPieceWaves = (V == PO_FWD_SH || V == PO_FWD_SG) && sizeof(T) * 3 * K <= 192 ? 4 : 1;
+
 template <typename T, int K, int VEC, int NL, int V, int SRC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_render_chunks(KBatch<1> B,
-                                                                                                    KSplit S) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kPieceWaves<T, K, V>, 8))) void k_render_chunks(
+    KBatch<1> B, KSplit S) {
     const int q = split_slot(S.count, S.region_slots);
     const int4 in = q < 0 ? make_int4(-1, 0, -1, 0) : S.info[q];
     const int h = in.x;
@@ -1261,8 +1267,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 }
 
 template <typename T, int K, int VEC, int NL, int V, int SRC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_render_subchunks(KBatch<1> B,
-                                                                                                       KSplit S) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kPieceWaves<T, K, V>, 8))) void k_render_subchunks(
+    KBatch<1> B, KSplit S) {
     const int q = split_slot(S.count2, S.region_slots);
     if (q < 0) return;
     const int4 in = S.info2[q];
