@@ -183,7 +183,7 @@ def _err(a, b):
 def cpu_baseline(scene, poses, frames32, frames16, budget_s=12.0, min_frames=5):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload: whole 800x800 frames of the poses in ERR_POSES (every 20th
-    pose), then of every 10th pose, until ~budget_s of work and at least
+    pose), then of the other poses, until ~budget_s of work and at least
     min_frames frames; scaled to frames per second.  The ERR_POSES frames give the per-channel error of
     the GPU's float32 and float16 renders (frames32, frames16: host images of
     those poses), and an oracle render of the float16-decoded tree on sampled
@@ -197,8 +197,8 @@ def cpu_baseline(scene, poses, frames32, frames16, budget_s=12.0, min_frames=5):
     f32 = [float(np.float32(v)) for v in (fx, fy, cx, cy)]
     n, dt, timed = 0, 0.0, []
     refs = {}
-    # the error poses first, then further poses (every 10th) until the budget
-    order = list(ERR_POSES) + [p for p in range(0, len(poses), 10) if p not in ERR_POSES]
+    # the error poses first, then the other poses until the budget
+    order = list(ERR_POSES) + [p for p in range(len(poses)) if p not in ERR_POSES]
     for p in order:
         if p not in ERR_POSES and dt >= budget_s and len(timed) >= min_frames:
             break
@@ -212,8 +212,8 @@ def cpu_baseline(scene, poses, frames32, frames16, budget_s=12.0, min_frames=5):
             refs[p] = rgb.reshape(H, W, 3)
     rays_per_s = n / dt
     base = {"value": rays_per_s / (W * H), "unit": "FPS", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{len(timed)} whole 800x800 frames of the same scene (poses every 20th, then every 10th, of "
-                      f"the 200), {dt:.1f} s of FP64 rendering, {rays_per_s / 1e6:.2f} Mrays/s"}
+            "sample": f"{len(timed)} whole 800x800 frames of the same scene (every 20th of the 200 poses, then "
+                      f"the others in order), {dt:.1f} s of FP64 rendering, {rays_per_s / 1e6:.2f} Mrays/s"}
     done = list(ERR_POSES)
     ref = np.stack([refs[p] for p in done])
     err = {"poses": done, "pixels": int(ref.size // 3),

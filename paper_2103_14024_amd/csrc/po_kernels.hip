@@ -911,12 +911,18 @@ __global__ __launch_bounds__(kBlock) void k_render_camera(KBatch<MAXJ> B) {
 // walk that finds its region full finishes in the lane that holds it.
 // ---------------------------------------------------------------------------
 
-// Queue region of this workgroup's claims.  Workgroup b runs on XCD b % 8,
-// which renders one band of the screen (xcd_swizzle); (b / 8) mod the region
-// count gives every region workgroups of all eight bands, so the regions
-// fill evenly even when the long walks crowd into the middle of the frame
-// (1920x1080 depth-9 frame: 1.93 against 2.03 ms with b mod the count).
-__device__ __forceinline__ int claim_region() { return (int)((blockIdx.x >> 3) % kSplitRegions); }
+// Queues are XCD-local: workgroup b runs on XCD b % 8 (the dispatcher deals
+// workgroups round-robin over the XCDs), claims its pieces in one of that
+// XCD's eight regions (8 x + (b / 8) mod 8), and the piece kernels take the
+// slots of XCD x's regions with workgroups that run on XCD x (split_slot).
+// A piece's head, its result and the join's reads of it then stay in the L2
+// of the XCD that wrote them (each XCD has its own L2).  The first walk
+// deals tile rows over the XCDs (xcd_interleave), so that every XCD gets a
+// share of the frame's long walks and its regions fill evenly.  Depth-9
+// 800x800 FP32: 0.586 against 0.631 ms with regions shared by all XCDs;
+// with XCD-local regions but contiguous screen bands per XCD, 1.01 ms (the
+// middle bands hold most long walks).
+__device__ __forceinline__ int claim_region() { return (int)((blockIdx.x & 7) * 8 + ((blockIdx.x >> 3) & 7)); }
 struct ContHead {
     double s;             // parameter where the first walk stopped (start of the next cell)
     float T, c0, c1, c2;  // transmittance and colour so far
@@ -1148,9 +1154,18 @@ __device__ __forceinline__ void first_walk(const KJob& J, const KSplit& S, int i
     }
 }
 
+// Logical workgroup of hardware workgroup b when runs of `chunk` logical
+// workgroups (a tile row) are dealt round-robin over the 8 XCDs: XCD x gets
+// runs x, x + 8, ...  The grid has 8 * chunk * ceil(ceil(n_logical / chunk) / 8)
+// workgroups; returns -1 for the padding ones.
+__device__ __forceinline__ int64_t xcd_interleave(int64_t b, int64_t n_logical, int64_t chunk) {
+    const int64_t x = b & 7, j = b >> 3;
+    const int64_t l = ((j / chunk) * 8 + x) * chunk + (j % chunk);
+    return l < n_logical ? l : -1;
+}
 template <typename T, int K, int VEC, int NL, int V>
 __global__ __launch_bounds__(kBlock) void k_render_camera_split(KBatch<1> B, KSplit S) {
-    const int64_t b = xcd_swizzle(blockIdx.x, B.n_blocks);
+    const int64_t b = xcd_interleave(blockIdx.x, B.n_blocks, 4 * B.job[0].tiles_x);
     if (b < 0) return;
     const KJob& J = B.job[0];
     const int q = (int)b;
@@ -1177,15 +1192,18 @@ __global__ void k_zero_i32(int32_t* __restrict__ p, int n) {
     if (i < n) p[i] = 0;
 }
 
-// Queue slot of this thread (workgroup blockIdx.x - first), or -1 beyond its
-// region's claimed slots.  Consecutive workgroups take consecutive slots of a
-// region (faster than interleaving the regions: 735 against 1035 us per
-// depth-9 frame).
+// Queue slot of this thread (workgroup blockIdx.x - first, first a multiple
+// of 8), or -1 beyond its region's claimed slots.  Workgroup b serves the
+// regions of its own XCD b % 8, and within it consecutive workgroups take
+// consecutive slots of a region (faster than interleaving the regions: 735
+// against 1035 us per depth-9 frame).
 __device__ __forceinline__ int split_slot(const int32_t* count, int region_slots, int first = 0) {
     const int b = (int)blockIdx.x - first;
     const int per = region_slots / kBlock;  // workgroups per region
-    const int region = b / per;
-    const int local = (b - region * per) * kBlock + (int)threadIdx.x;
+    const int x = b & 7, j = b >> 3;
+    const int r8 = j / per;
+    const int region = x * 8 + r8;
+    const int local = (j - r8 * per) * kBlock + (int)threadIdx.x;
     const int n = min(count[region], region_slots);
     return local < n ? region * region_slots + local : -1;
 }
@@ -2074,7 +2092,12 @@ hipError_t split_t(const po_tree* t, const KJob& job, int n_blocks, int variant,
     // counters cleared by a kernel rather than a memset node, so that the
     // launches can also be captured in a graph
     hipLaunchKernelGGL(k_zero_i32, dim3(2), dim3(kSplitRegions), 0, s, S.count, 2 * kSplitRegions);
-    dim3 g1((unsigned)grid_for(n_blocks)), g2((unsigned)(kSplitRegions * (S.region_slots / kBlock))), blk(kBlock);
+    int64_t g1n = grid_for(n_blocks);
+    if constexpr (SRC == 0) {  // tile rows dealt over the XCDs (xcd_interleave)
+        const int64_t ch = 4 * (int64_t)job.tiles_x, nch = (n_blocks + ch - 1) / ch;
+        g1n = 8 * ch * ((nch + 7) / 8);
+    }
+    dim3 g1((unsigned)g1n), g2((unsigned)(kSplitRegions * (S.region_slots / kBlock))), blk(kBlock);
     const size_t lds = stack_bytes(job.tr.depth);
     const bool fast = use_fast<T, K>(t);
 #define PO_SPLIT(VEC_, NL_, V_)                                                                        \
