@@ -99,7 +99,7 @@ constexpr int kSplitRegionSlots = PO_SPLIT_REGION_SLOTS;
 constexpr int kNoAllocRegionSlots = 8192;
 constexpr int kSplitMaxChunks = 16;
 #ifndef PO_SPLIT_STEPS
-#define PO_SPLIT_STEPS 24
+#define PO_SPLIT_STEPS 28
 #endif
 #ifndef PO_CHUNK_STEPS
 #define PO_CHUNK_STEPS 24
