@@ -164,6 +164,53 @@ def measure_one_pass(po, tree, cams, steps, warmup, stream):
     return {"fps": round(steps / (ms * 1e-3), 2), "ms_per_step": round(ms / steps, 4)}
 
 
+def measure_end_to_end(po, tree, cams, steps, warmup, stream):
+    """Frames delivered to the host: each render followed by the copy of its
+    800x800x3 float32 image into pinned host memory.  "serial" copies on the
+    render stream (render, copy, render, ...); "overlapped" copies on a second
+    stream from two image buffers, so that a frame's copy runs beside the next
+    frame's render.  Not the headline: the boundary takes device buffers."""
+    import torch
+
+    imgs = [torch.empty((H, W, 3), dtype=torch.float32, device="cuda") for _ in range(2)]
+    hosts = [torch.empty((H, W, 3), dtype=torch.float32, pin_memory=True) for _ in range(2)]
+    order = timed_poses(steps, len(cams))
+    copy_stream = torch.cuda.Stream()
+    res = {}
+    for mode in ("serial", "overlapped"):
+        for rep in range(2):  # the first pass warms up
+            n = warmup if rep == 0 else steps
+            torch.cuda.synchronize()
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            done = [None, None]
+            t0.record(stream)
+            for i in range(n):
+                k = i % 2 if mode == "overlapped" else 0
+                if done[k] is not None:
+                    stream.wait_event(done[k])
+                po.render_camera(tree, cams[order[i % len(order)]], stop_T=STOP_T, out=imgs[k], stream=stream)
+                if mode == "serial":
+                    with torch.cuda.stream(stream):
+                        hosts[0].copy_(imgs[0], non_blocking=True)
+                    continue
+                ready = torch.cuda.Event()
+                ready.record(stream)
+                copy_stream.wait_event(ready)
+                with torch.cuda.stream(copy_stream):
+                    hosts[k].copy_(imgs[k], non_blocking=True)
+                done[k] = torch.cuda.Event()
+                done[k].record(copy_stream)
+            for e in done:
+                if e is not None:
+                    stream.wait_event(e)
+            t1.record(stream)
+            torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        res[mode] = {"fps": round(steps / (ms * 1e-3), 2), "ms_per_step": round(ms / steps, 4)}
+    res["bytes_per_frame"] = H * W * 3 * 4
+    return res
+
+
 ERR_POSES = list(range(0, N_POSES, 20))   # poses whose frames the oracle renders (error and CPU baseline)
 
 
@@ -178,6 +225,17 @@ def gpu_frames(po, tree, cams, poses):
 def _err(a, b):
     e = np.abs(np.asarray(a, np.float64) - np.asarray(b, np.float64)).reshape(-1, 3)
     return {"max": [round(float(v), 8) for v in e.max(0)], "mean": [float("%.3e" % v) for v in e.mean(0)]}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(scene, poses, frames32, frames16, budget_s=12.0, min_frames=5):
@@ -214,6 +272,20 @@ def cpu_baseline(scene, poses, frames32, frames16, budget_s=12.0, min_frames=5):
     base = {"value": rays_per_s / (W * H), "unit": "FPS", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{len(timed)} whole 800x800 frames of the same scene (every 20th of the 200 poses, then "
                       f"the others in order), {dt:.1f} s of FP64 rendering, {rays_per_s / 1e6:.2f} Mrays/s"}
+    # one core: rows 320-479 (the middle of the image) of the first error pose
+    threads = oracle.num_threads()
+    o, d = oracle.camera_rays(np.asarray(poses[ERR_POSES[0]], np.float32).astype(np.float64), W, H, *f32)
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        t.render_rays(o[320 * W:480 * W], d[320 * W:480 * W], gamma=STOP_T)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    base["single_core"] = {"mrays_per_s": round(160 * W / dt1 / 1e6, 4), "fps": round(160 * W / dt1 / (W * H), 4),
+                           "sample": f"rows 320-479 of pose {ERR_POSES[0]}, {dt1:.2f} s"}
+    base["nproc"] = len(os.sched_getaffinity(0))
+    base["cpu_model"] = _cpu_model()
     done = list(ERR_POSES)
     ref = np.stack([refs[p] for p in done])
     err = {"poses": done, "pixels": int(ref.size // 3),
@@ -540,6 +612,9 @@ def main():
     frames32 = {} if args.no_cpu_baseline else gpu_frames(po, tree32, cams, ERR_POSES)
     one32 = measure_one_pass(po, tree32, cams, args.steps, args.warmup, stream)
     log(f"fp32 one pass: {one32['fps']:.1f} FPS")
+    e2e = None if args.no_extra else measure_end_to_end(po, tree32, cams, args.steps, args.warmup, stream)
+    if e2e:
+        log(f"fp32 with the image copied to the host: {e2e}")
     tb = counter_traffic("f32")
     traffic_gbps = None if tb is None else round(tb / (r32["ms_per_step"] * 1e-3) / 1e9, 1)
     out = {
@@ -555,6 +630,7 @@ def main():
         "child_entry_reads_per_ray": round(r32["node_loads_per_ray"], 2),
         "lane_efficiency": round(r32["lane_efficiency"], 4),
         "one_pass": one32,
+        "end_to_end_with_d2h": e2e,
         "roofline": {"bound": "hbm", "achieved": round(r32["alg_gbps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(r32["alg_gbps"] / HBM_PEAK_GBPS, 4), "traffic": traffic_gbps,
                      "kernel": "render pass <float,16,16,48,SH>: k_zero_i32, k_render_camera_split, "

@@ -750,8 +750,10 @@ static po_status render_camera_impl(const po_tree* t, const po_camera* cam, cons
                        j.op.max_steps > PO_SPLIT_STEPS;
     if (split && noalloc) {
         if ((e = po_noalloc_queue(&S)) != hipSuccess) return device_fail(e, "locating the fixed work queue");
+        S.split_steps = po_camera_split_steps(4 * (int64_t)tiles_of(cam));
         e = po_launch_camera_split(t, j, 4 * tiles_of(cam), variant, S, (hipStream_t)stream);
     } else if (split && split_queue(stream, &S)) {
+        S.split_steps = po_camera_split_steps(4 * (int64_t)tiles_of(cam));
         e = po_launch_camera_split(t, j, 4 * tiles_of(cam), variant, S, (hipStream_t)stream);
     } else {
         e = po_launch_camera_jobs(t, 1, &j, 4 * tiles_of(cam), variant, (hipStream_t)stream);

@@ -79,6 +79,34 @@ class Trainer:
         return loss
 
 
+    def save(self, path) -> None:
+        """Checkpoints the fit: the tree's values, the step count and the
+        batch generator's state (written with Tree.save)."""
+        self.tree.save(path, step=self.steps, rng_state=self.gen.get_state().numpy())
+
+    def load(self, path) -> None:
+        """Resumes from a file written by save: the leaf values are copied into
+        this trainer's tree in place (its structure must match the file's), and
+        the step count and the generator state are restored."""
+        import numpy as np
+        import torch
+
+        from .tree import read_checkpoint
+
+        f, meta = read_checkpoint(path)
+        tr = self.tree
+        if (f["depth"] != tr.depth or f["sh_degree"] != tr.sh_degree or f["sigma"].dtype != np.float32
+                or tuple(f["sh"].shape) != tuple(tr.sh.shape)
+                or not np.array_equal(f["child"], tr.child.cpu().numpy())):
+            raise ValueError("checkpoint tree does not match the trainer's tree")
+        if "step" not in meta or "rng_state" not in meta:
+            raise ValueError("checkpoint lacks the trainer state")
+        tr.sigma.copy_(torch.from_numpy(f["sigma"]))
+        tr.sh.copy_(torch.from_numpy(f["sh"]))
+        self.steps = int(meta["step"])
+        self.gen.set_state(torch.from_numpy(np.ascontiguousarray(meta["rng_state"], np.uint8)))
+
+
 def training_set(gt_tree, cams, bg=(1.0, 1.0, 1.0), stop_T=1e-4, device="cuda"):
     """Rays of all pixels of `cams` and their colours rendered from gt_tree:
     (origins, dirs, target), each (sum H*W, 3) float32 on `device`."""

@@ -81,15 +81,93 @@ def build_host(depth, sh_degree, cells, center=(0.0, 0.0, 0.0), half=1.0):
     return child, perm
 
 
-def validate_host(depth, sh_degree, child, n_leaves, sigma=None, dtype=L.PO_F32, center=(0, 0, 0), half=1.0) -> None:
+def validate_host(depth, sh_degree, child, n_leaves, sigma=None, dtype=L.PO_F32, center=(0, 0, 0), half=1.0,
+                  sh_stride=0) -> None:
     """Checks a host child array (and optional densities); raises PlenOctreeError."""
     child = np.ascontiguousarray(np.asarray(child, np.int32).reshape(-1, 8))
-    desc = make_desc(depth, sh_degree, center, half, dtype)
+    desc = make_desc(depth, sh_degree, center, half, dtype, sh_stride)
     sp = None
     if sigma is not None:
         sigma = np.ascontiguousarray(np.asarray(sigma, np.float16 if dtype == L.PO_F16 else np.float32))
         sp = sigma.ctypes.data
     L.call("po_tree_validate", ctypes.byref(desc), child.shape[0], child.ctypes.data, int(n_leaves), sp)
+
+
+CHECKPOINT_VERSION = 1
+_CKPT_LEAF_DTYPES = {"sigma": (np.float32, np.float16), "sh": (np.float32, np.float16, np.int16)}
+
+
+def write_checkpoint(path, fields: dict, meta: dict | None = None) -> None:
+    """Writes a tree as an uncompressed .npz of plain arrays (nothing pickled).
+
+    fields: depth, sh_degree, center (3,), half, child (n_nodes, 8) int32,
+    sigma (n,) float32/float16, sh (n, stride) float32/float16 (int16 codebook
+    positions), and optionally perm (n,) int64, lobes (K, 4) float32,
+    codebook (K, M, 4) float16.  meta: extra numeric scalars or arrays (a step
+    count, a seed, a generator state), stored under "meta_<name>"."""
+    arrays = {"version": np.int32(CHECKPOINT_VERSION),
+              "depth": np.int32(fields["depth"]), "sh_degree": np.int32(fields["sh_degree"]),
+              "center": np.asarray(fields["center"], np.float64).reshape(3), "half": np.float64(fields["half"]),
+              "child": np.ascontiguousarray(fields["child"])}
+    for k in ("sigma", "sh", "perm", "lobes", "codebook"):
+        if fields.get(k) is not None:
+            arrays[k] = np.ascontiguousarray(fields[k])
+    for k, v in (meta or {}).items():
+        a = np.asarray(v)
+        if a.dtype.kind not in "biuf":
+            raise TypeError(f"checkpoint meta {k!r} must be numeric")
+        arrays["meta_" + k] = a
+    with open(path, "wb") as f:
+        np.savez(f, **arrays)
+
+
+def read_checkpoint(path):
+    """Reads a file written by write_checkpoint with NumPy's non-pickling
+    loader and checks its structure (shapes, dtypes and the child array, with
+    the library's validator) before anything reaches a device.
+
+    Returns (fields, meta) as host arrays; raises ValueError or
+    PlenOctreeError on a malformed file."""
+    with np.load(path, allow_pickle=False) as z:
+        a = {k: z[k] for k in z.files}
+    for k in ("version", "depth", "sh_degree", "center", "half", "child", "sigma", "sh"):
+        if k not in a:
+            raise ValueError(f"checkpoint lacks {k!r}")
+    if int(a["version"]) != CHECKPOINT_VERSION:
+        raise ValueError(f"checkpoint version {int(a['version'])}, expected {CHECKPOINT_VERSION}")
+    depth, deg = int(a["depth"]), int(a["sh_degree"])
+    child, sigma, sh = a["child"], a["sigma"], a["sh"]
+    for k, ok in _CKPT_LEAF_DTYPES.items():
+        if a[k].dtype not in [np.dtype(t) for t in ok]:
+            raise ValueError(f"checkpoint {k} has dtype {a[k].dtype}")
+    if child.dtype != np.int32 or child.ndim != 2 or child.shape[1] != 8:
+        raise ValueError("checkpoint child must be (n_nodes, 8) int32")
+    n, K = sigma.shape[0], n_coef(deg)
+    codebook = a.get("codebook")
+    if sigma.ndim != 1 or sh.ndim != 2 or sh.shape[0] != n or sh.shape[1] < (K if codebook is not None else 3 * K):
+        raise ValueError("checkpoint sigma/sh shapes do not match the leaf count and SH degree")
+    if codebook is None and sh.dtype != sigma.dtype:
+        raise ValueError("checkpoint sigma and sh must share a dtype")
+    if "perm" in a and (a["perm"].dtype != np.int64 or a["perm"].shape != (n,)):
+        raise ValueError("checkpoint perm must be (n_leaves,) int64")
+    if "lobes" in a and (a["lobes"].dtype != np.float32 or a["lobes"].shape != (K, 4)):
+        raise ValueError(f"checkpoint lobes must be ({K}, 4) float32")
+    if codebook is not None and (codebook.dtype != np.float16 or codebook.ndim != 3 or codebook.shape[0] != K
+                                 or codebook.shape[2] != 4 or sh.dtype != np.int16 or sigma.dtype != np.float16):
+        raise ValueError("checkpoint codebook trees take float16 sigma, int16 records and a (K, M, 4) float16 codebook")
+    center, half = tuple(float(c) for c in a["center"]), float(a["half"])
+    if codebook is None:
+        validate_host(depth, deg, child, n, sigma, L.PO_F16 if sigma.dtype == np.float16 else L.PO_F32, center, half,
+                      sh.shape[1])
+    else:
+        # records of 16-bit codebook positions: the structure is checked alone
+        validate_host(depth, deg, child, n, None, L.PO_F32, center, half)
+        if not np.isfinite(sigma).all():
+            raise ValueError("checkpoint densities must be finite")
+    fields = {"depth": depth, "sh_degree": deg, "center": center, "half": half, "child": child, "sigma": sigma, "sh": sh,
+              "perm": a.get("perm"), "lobes": a.get("lobes"), "codebook": codebook}
+    meta = {k[5:]: v for k, v in a.items() if k.startswith("meta_")}
+    return fields, meta
 
 
 class Tree:
@@ -234,6 +312,27 @@ class Tree:
         t_idx = torch.from_numpy(np.ascontiguousarray(idx[perm]).view(np.int16)).to(dev)
         t_cb = torch.from_numpy(cb.view(np.float16)).to(dev)
         return cls(depth, sh_degree, t_child, t_sig, t_idx, center, half, perm=perm, codebook=t_cb, index=index)
+
+    def save(self, path, **meta) -> None:
+        """Writes the tree (structure, leaf values, leaf order, basis lobes or
+        codebook) to an .npz file; meta: extra numeric values to store."""
+        t = lambda x: None if x is None else x.detach().cpu().numpy()  # noqa: E731
+        write_checkpoint(path, {"depth": self.depth, "sh_degree": self.sh_degree, "center": self.center,
+                                "half": self.half, "child": t(self.child), "sigma": t(self.sigma), "sh": t(self.sh),
+                                "perm": self.perm, "lobes": t(self.lobes), "codebook": t(self.codebook)}, meta)
+
+    @classmethod
+    def load(cls, path, device="cuda", index=True):
+        """Reads a file written by save (checked on the host first) and binds
+        it on `device`.  Returns (tree, meta)."""
+        import torch
+
+        f, meta = read_checkpoint(path)
+        dev = torch.device(device)
+        up = lambda x: None if x is None else torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+        tree = cls(f["depth"], f["sh_degree"], up(f["child"]), up(f["sigma"]), up(f["sh"]), f["center"], f["half"],
+                   perm=f["perm"], lobes=up(f["lobes"]), codebook=up(f["codebook"]), index=index)
+        return tree, meta
 
     def leaf_values(self):
         """(sigma (n,), sh (n, 3, K)) as float32 NumPy arrays in the caller's cell
