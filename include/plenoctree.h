@@ -328,6 +328,31 @@ po_status po_render_rays_backward(const po_tree* t, int64_t n, const float* d_or
                                   const float* d_rgb_fwd, const float* d_grad_rgb,
                                   float* d_grad_sigma, float* d_grad_sh, void* stream);
 
+/* po_render_rays_keep and po_render_rays_backward_kept: the render and the
+ * gradient of one ray batch as the two passes of App. B.3, where the second
+ * pass reuses the pieces of the first instead of walking them forward again.
+ * po_render_rays_keep renders like po_render_rays (no aux outputs or viewer
+ * options; float32 trees) and leaves its pieces, with their forward results,
+ * in the stream's work queue; d_ray_slot [n] int32 (device, caller-owned,
+ * overwritten) records which rays it handed on.  po_render_rays_backward_kept
+ * then accumulates the same gradient as po_render_rays_backward with d_rgb_fwd
+ * from that render, without the forward pass over the pieces.  The backward
+ * must be called on the same stream with the same tree, n, ray arrays,
+ * d_ray_slot and options, and no other split render, split backward or kept
+ * render may run on that stream's queue in between (the library checks these
+ * on the host and returns PO_ERR_INVALID otherwise; it cannot check that the
+ * contents of the arrays are unchanged).  One backward consumes the kept
+ * pieces.  Below 65536 rays, or with PO_ONE_PASS, both run in one pass.
+ * Errors: PO_ERR_INVALID, PO_ERR_UNSUPPORTED (tree not PO_F32, aux, sh_off or
+ * clip set), PO_ERR_DEVICE. */
+po_status po_render_rays_keep(const po_tree* t, int64_t n, const float* d_origins, const float* d_dirs,
+                              const po_render_opts* opts, float* d_rgb, int32_t* d_ray_slot, void* stream);
+po_status po_render_rays_backward_kept(const po_tree* t, int64_t n, const float* d_origins,
+                                       const float* d_dirs, const po_render_opts* opts,
+                                       const float* d_rgb_fwd, const float* d_grad_rgb,
+                                       float* d_grad_sigma, float* d_grad_sh, const int32_t* d_ray_slot,
+                                       void* stream);
+
 /* ------------------------------------------------------------ optimisation
  * Direct optimisation of the leaf values (Sec. 4.3; App. B.5): the NeRF
  * loss of Sec. 3 (eqn:nerfloss), reduced here as a mean over the batch and

@@ -73,6 +73,8 @@ _SIGS = {
     "po_render_camera": [_P, ctypes.POINTER(po_camera), ctypes.POINTER(po_render_opts), _P, _P, _P],
     "po_render_camera_noalloc": [_P, ctypes.POINTER(po_camera), ctypes.POINTER(po_render_opts), _P, _P, _P],
     "po_render_rays_backward": [_P, _I64, _P, _P, ctypes.POINTER(po_render_opts), _P, _P, _P, _P, _P],
+    "po_render_rays_keep": [_P, _I64, _P, _P, ctypes.POINTER(po_render_opts), _P, _P, _P],
+    "po_render_rays_backward_kept": [_P, _I64, _P, _P, ctypes.POINTER(po_render_opts), _P, _P, _P, _P, _P, _P],
     "po_render_batch": [_I32, ctypes.POINTER(po_job), _P],
     "po_camera_tiles": [ctypes.POINTER(po_camera), ctypes.POINTER(_I32)],
     "po_camera_rays": [ctypes.POINTER(po_camera), _P, _P, _P],

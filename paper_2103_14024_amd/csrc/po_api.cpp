@@ -64,12 +64,30 @@ constexpr int64_t kSplitMinBackward = PO_SPLIT_MIN_BACKWARD;
 std::mutex g_split_mu;
 std::map<std::pair<int, void*>, void*> g_split;
 
+// The last kept ray-list render on a queue (po_render_rays_keep): its pieces
+// stay valid until the next split launch on that queue or the backward that
+// consumes them.  Guarded by g_split_mu.
+struct Kept {
+    bool valid = false, split = false;
+    const po_tree* t = nullptr;
+    int64_t n = 0;
+    const float* o = nullptr;
+    const float* d = nullptr;
+    const int32_t* slot = nullptr;
+    po_render_opts opts;
+};
+std::map<std::pair<int, void*>, Kept> g_kept;
+
+// The queue of (current device, stream), allocated on first use; every
+// split launch takes it through here, which ends the validity of a kept
+// render's pieces in it.
 bool split_queue(void* stream, KSplit* S) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
     void* base = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_split_mu);
+        g_kept[{dev, stream}].valid = false;
         auto it = g_split.find({dev, stream});
         if (it != g_split.end()) {
             base = it->second;
@@ -113,6 +131,7 @@ void po_split_layout(void* base, int region_slots, KSplit* S) {
     S->ray_o = nullptr;
     S->ray_d = nullptr;
     S->n_rays = 0;
+    S->ray_slot = nullptr;
 }
 
 namespace {
@@ -799,6 +818,92 @@ po_status po_render_rays_backward(const po_tree* t, int64_t n, const float* d_or
     return ok();
 }
 
+po_status po_render_rays_keep(const po_tree* t, int64_t n, const float* d_origins, const float* d_dirs,
+                              const po_render_opts* opts, float* d_rgb, int32_t* d_ray_slot, void* stream) {
+    if (!t) return fail(PO_ERR_INVALID, "tree is NULL");
+    if (po_status s = check_opts(opts)) return s;
+    if (t->desc.dtype != PO_F32) return fail(PO_ERR_UNSUPPORTED, "a kept render is for gradients, which need float32 leaves");
+    if (opts->flags & PO_OUT_AUX) return fail(PO_ERR_UNSUPPORTED, "a kept render writes no aux outputs");
+    if (po_view_opts(kopts(t, opts), nullptr))
+        return fail(PO_ERR_UNSUPPORTED, "gradients of renders with sh_off or a slicing plane are not provided");
+    if (n < 0 || n > (1ll << 40)) return fail(PO_ERR_INVALID, "n = %lld out of range", (long long)n);
+    if (n == 0) return ok();
+    if (!d_origins || !d_dirs || !d_rgb || !d_ray_slot) return fail(PO_ERR_INVALID, "NULL array");
+    int dev = 0;
+    if (hipError_t e = hipGetDevice(&dev)) return device_fail(e, "hipGetDevice");
+    const KOpts k = kopts(t, opts);
+    KSplit S;
+    bool split = !(k.flags & PO_ONE_PASS) && n >= kSplitMinRays && n < (1ll << 31) && k.max_steps > PO_SPLIT_STEPS &&
+                 split_queue(stream, &S);
+    hipError_t e;
+    if (split) {
+        S.ray_slot = d_ray_slot;
+        e = po_launch_rays_split(t, n, d_origins, d_dirs, k, d_rgb, nullptr, S, (hipStream_t)stream);
+    } else {
+        e = po_launch_rays(t, n, d_origins, d_dirs, k, d_rgb, nullptr, (hipStream_t)stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "render_rays_keep launch");
+    std::lock_guard<std::mutex> lk(g_split_mu);
+    Kept& kp = g_kept[{dev, stream}];
+    kp.valid = true;
+    kp.split = split;
+    kp.t = t;
+    kp.n = n;
+    kp.o = d_origins;
+    kp.d = d_dirs;
+    kp.slot = d_ray_slot;
+    kp.opts = *opts;
+    return ok();
+}
+
+po_status po_render_rays_backward_kept(const po_tree* t, int64_t n, const float* d_origins, const float* d_dirs,
+                                       const po_render_opts* opts, const float* d_rgb_fwd, const float* d_grad_rgb,
+                                       float* d_grad_sigma, float* d_grad_sh, const int32_t* d_ray_slot,
+                                       void* stream) {
+    if (!t) return fail(PO_ERR_INVALID, "tree is NULL");
+    if (po_status s = check_opts(opts)) return s;
+    if (t->desc.dtype != PO_F32) return fail(PO_ERR_UNSUPPORTED, "gradients need float32 leaves");
+    if (n < 0 || n > (1ll << 40)) return fail(PO_ERR_INVALID, "n = %lld out of range", (long long)n);
+    if (n == 0) return ok();
+    if (!d_origins || !d_dirs || !d_rgb_fwd || !d_grad_rgb || !d_grad_sigma || !d_grad_sh || !d_ray_slot)
+        return fail(PO_ERR_INVALID, "NULL array");
+    int dev = 0;
+    if (hipError_t e = hipGetDevice(&dev)) return device_fail(e, "hipGetDevice");
+    Kept kp;
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_split_mu);
+        auto it = g_kept.find({dev, stream});
+        if (it == g_kept.end() || !it->second.valid || it->second.t != t || it->second.n != n ||
+            it->second.o != d_origins || it->second.d != d_dirs || it->second.slot != d_ray_slot ||
+            std::memcmp(&it->second.opts, opts, sizeof *opts) != 0)
+            return fail(PO_ERR_INVALID,
+                        "no kept render of these rays is pending on this stream: po_render_rays_keep must be the last "
+                        "split work on the stream's queue, with the same tree, n, arrays, ray_slot and options");
+        kp = it->second;
+        it->second.valid = false;  // the prefix pass overwrites the pieces' results
+        if (kp.split) {
+            auto q = g_split.find({dev, stream});
+            if (q == g_split.end()) return fail(PO_ERR_INVALID, "the kept render's queue was released");
+            base = q->second;
+        }
+    }
+    const KOpts k = kopts(t, opts);
+    hipError_t e;
+    if (kp.split) {
+        KSplit S;
+        po_split_layout(base, kSplitRegionSlots, &S);
+        S.ray_slot = const_cast<int32_t*>(d_ray_slot);
+        e = po_launch_backward_kept(t, n, d_origins, d_dirs, k, d_rgb_fwd, d_grad_rgb, d_grad_sigma, d_grad_sh, S,
+                                    (hipStream_t)stream);
+    } else {
+        e = po_launch_backward(t, n, d_origins, d_dirs, k, d_rgb_fwd, d_grad_rgb, d_grad_sigma, d_grad_sh,
+                               (hipStream_t)stream);
+    }
+    if (e != hipSuccess) return device_fail(e, "backward_kept launch");
+    return ok();
+}
+
 po_status po_camera_rays(const po_camera* cam, float* d_origins, float* d_dirs, void* stream) {
     if (po_status s = check_camera(cam)) return s;
     if (!d_origins || !d_dirs) return fail(PO_ERR_INVALID, "NULL array");
@@ -881,6 +986,7 @@ po_status po_render_batch(int32_t n_jobs, const po_job* jobs, void* stream) {
         kj.tile_begin = J.tile_begin;
         kj.block_begin = 0;
         kj.tiles_x = (J.cam.width + PO_TILE - 1) / PO_TILE;
+        S.split_steps = po_camera_split_steps(4 * (int64_t)nt);
         hipError_t e = po_launch_camera_split(J.tree, kj, 4 * nt, variant(i) % 4, S, (hipStream_t)stream);
         if (e != hipSuccess) return device_fail(e, "render_batch launch");
     }
@@ -990,6 +1096,7 @@ po_status po_release_queues(void) {
         if (e != hipSuccess && first == hipSuccess) first = e;
     }
     g_split.clear();
+    g_kept.clear();
     if (have_cur) (void)hipSetDevice(cur);
     if (first != hipSuccess) return device_fail(first, "releasing the split-render queues");
     return ok();

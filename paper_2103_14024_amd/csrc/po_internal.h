@@ -158,6 +158,7 @@ struct KSplit {
     const float* ray_o;    // ray-list renders: origins [n_rays][3] (camera renders: unused)
     const float* ray_d;    // ray-list renders: directions [n_rays][3]
     int64_t n_rays;
+    int32_t* ray_slot;     // kept ray-list render: [n_rays] first chunk slot of each ray, -1 if not handed on
 };
 // Piece sizes of a split pass over a list of n rays.  The render and the
 // backward of the same rays cut them alike: the transmittance in front of
@@ -231,6 +232,13 @@ hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, con
 hipError_t po_launch_backward_split(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
                                     const float* rgb_fwd, const float* grad, float* gsig, float* gsh,
                                     const KSplit& S, hipStream_t s);
+// Backward of the n rays of a kept split render (po_launch_rays_split with
+// S.ray_slot set, same rays, options and queue, nothing else on the queue in
+// between): the first walk, the prefixes of the render's own pieces, then
+// the backward of the pieces.  Consumes the kept pieces.
+hipError_t po_launch_backward_kept(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
+                                   const float* rgb_fwd, const float* grad, float* gsig, float* gsh,
+                                   const KSplit& S, hipStream_t s);
 hipError_t po_launch_camera_rays(const KCam& cam, float* o, float* d, hipStream_t s);
 // Visibility filter: mode 0 alpha, 1 contribution; weight[n_leaves] raised in place, alpha[H*W] or nullptr.
 hipError_t po_launch_leaf_weights(const po_tree* t, const KCam& cam, const KOpts& op, int mode, float* weight,

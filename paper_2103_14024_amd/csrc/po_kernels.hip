@@ -1151,6 +1151,10 @@ __device__ __forceinline__ void first_walk(const KJob& J, const KSplit& S, int i
         }
     }
     const size_t p = (size_t)idx;
+    if constexpr (SRC == 1) {
+        // a kept render records which rays it handed on, for its backward
+        if (valid && S.ray_slot) S.ray_slot[p] = handed ? h : -1;
+    }
     if (valid && !handed) {
         J.rgb[3 * p + 0] = fmaf(smp.Tl, op.bg[0], smp.c0);
         J.rgb[3 * p + 1] = fmaf(smp.Tl, op.bg[1], smp.c1);
@@ -1682,6 +1686,46 @@ __global__ __launch_bounds__(kBlock) void k_backward_split(KBatch<1> B, KSplit S
     }
 }
 
+// The backward's first walk over the rays of a kept render
+// (po_render_rays_keep): the render's pieces, their heads (s, T and the
+// colour prefix P after its first walk) and ray_slot stay in the queue, so
+// a ray the render handed on is differentiated over the same first
+// split_steps cells and its pieces are not walked forward again; a ray it
+// did not hand on (ended within the first walk, or its region was full) is
+// differentiated to its end here.
+template <int K, int VEC, int NL>
+__global__ __launch_bounds__(kBlock) void k_backward_first_kept(KBatch<1> B, KSplit S,
+                                                                const float* __restrict__ rgb_fwd,
+                                                                const float* __restrict__ grad,
+                                                                float* __restrict__ gsig, float* __restrict__ gsh) {
+    const int64_t b = xcd_swizzle(blockIdx.x, B.n_blocks);
+    if (b < 0) return;
+    const int64_t i = b * kBlock + threadIdx.x;
+    const KJob& J = B.job[0];
+    const KTree& tr = J.tr;
+    using Smp = BwdSampler<K, VEC, NL>;
+    Smp smp;
+    __shared__ float s_prod[kBlock * Smp::SW];
+    __shared__ int s_leaf[kBlock];
+    extern __shared__ int po_stack[];
+    Ray r;
+    bool live = false, handed = false;
+    if (i < S.n_rays) {
+        double ro[3], rd[3];
+        ray_of<1>(J, S, (int)i, ro, rd);
+        if (ray_setup(tr, ro, rd, r)) {
+            bwd_init<K>(smp, tr, J.op, r, (size_t)i, rgb_fwd, grad, gsig, gsh, s_prod, s_leaf);
+            live = !(smp.g0 == 0.0f && smp.g1 == 0.0f && smp.g2 == 0.0f);
+            handed = S.ray_slot[i] >= 0;
+        }
+    }
+    if (live) {
+        const int cap = handed ? min(S.split_steps, J.op.max_steps) : J.op.max_steps;
+        const int steps = march<Smp, true>(tr, r, cap, po_stack + threadIdx.x, smp);
+        if (r.more & (steps >= J.op.max_steps)) atomicAdd(&g_po_errors, 1ull);  // the step cap proper
+    }
+}
+
 // Prefix of one piece: its forward result o is replaced by (P, T) in front
 // of it and whether it lies before the early stop (Tlast 1) or not (-1).
 template <int K, int VEC, int NL, int V>
@@ -1780,6 +1824,7 @@ __global__ __launch_bounds__(kBlock) void k_backward_pieces(KBatch<1> B, KSplit 
     __shared__ float s_prod[kBlock * BwdSampler<K, VEC, NL>::SW];
     __shared__ int s_leaf[kBlock];
     bwd_init<K>(smp, J.tr, J.op, r, (size_t)idx, rgb_fwd, grad, gsig, gsh, s_prod, s_leaf);
+    if (smp.g0 == 0.0f && smp.g1 == 0.0f && smp.g2 == 0.0f) return;  // (a kept render's rays without gradient)
     smp.Tl = o.T;
     smp.P0 = o.c0;
     smp.P1 = o.c1;
@@ -2189,6 +2234,47 @@ hipError_t backward_split_t(const po_tree* t, int64_t n, const float* o, const f
     return hipGetLastError();
 }
 
+// The backward of a kept render: its pieces and their forward results are in
+// the queue already, so the chunk and sub-chunk kernels are not run again
+// and the counters are not cleared.
+template <int K>
+hipError_t backward_kept_t(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
+                           const float* rgb_fwd, const float* grad, float* gsig, float* gsh, const KSplit& S0,
+                           hipStream_t s) {
+    using P = Plan<float, K>;
+    KBatch<1> B;
+    std::memset(&B, 0, sizeof B);
+    B.job[0].tr = t->kt;
+    B.job[0].op = op;
+    B.n_jobs = 1;
+    B.n_blocks = (int)((n + kBlock - 1) / kBlock);
+    KSplit S = S0;
+    S.ray_o = o;
+    S.ray_d = d;
+    S.n_rays = n;
+    dim3 g1((unsigned)grid_for(B.n_blocks)), g2((unsigned)(kSplitRegions * (S.region_slots / kBlock))),
+        g3(2u * g2.x), blk(kBlock);
+    const size_t lds = stack_bytes(t->kt.depth);
+    const bool sg = t->kt.lobes != nullptr;
+    po_rays_piece_sizes(n, &S);
+#define PO_BKEPT(VEC_, NL_)                                                                                       \
+    do {                                                                                                         \
+        hipLaunchKernelGGL((k_backward_first_kept<K, VEC_, NL_>), g1, blk, lds, s, B, S, rgb_fwd, grad, gsig,    \
+                           gsh);                                                                                 \
+        if (sg)                                                                                                  \
+            hipLaunchKernelGGL((k_piece_prefix<K, VEC_, NL_, PO_FWD_SG>), g2, blk, lds, s, B, S);                \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_piece_prefix<K, VEC_, NL_, PO_FWD_SH>), g2, blk, lds, s, B, S);                \
+        hipLaunchKernelGGL((k_backward_pieces<K, VEC_, NL_>), g3, blk, lds, s, B, S, rgb_fwd, grad, gsig, gsh);  \
+    } while (0)
+    if (use_fast<float, K>(t))
+        PO_BKEPT(P::FAST_VEC, P::FAST_NL);
+    else
+        PO_BKEPT(4, P::GEN_NL);
+#undef PO_BKEPT
+    return hipGetLastError();
+}
+
 template <int K>
 hipError_t backward_t(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
                       const float* rgb_fwd, const float* grad, float* gsig, float* gsh, hipStream_t s) {
@@ -2311,6 +2397,12 @@ hipError_t po_launch_backward_split(const po_tree* t, int64_t n, const float* o,
                                     const float* rgb_fwd, const float* grad, float* gsig, float* gsh,
                                     const KSplit& S, hipStream_t s) {
     PO_DISPATCH_K(t->K, (backward_split_t<KK>(t, n, o, d, op, rgb_fwd, grad, gsig, gsh, S, s)));
+}
+
+hipError_t po_launch_backward_kept(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
+                                   const float* rgb_fwd, const float* grad, float* gsig, float* gsh,
+                                   const KSplit& S, hipStream_t s) {
+    PO_DISPATCH_K(t->K, (backward_kept_t<KK>(t, n, o, d, op, rgb_fwd, grad, gsig, gsh, S, s)));
 }
 #endif
 

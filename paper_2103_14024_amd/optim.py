@@ -3,10 +3,11 @@
 The tree structure is fixed; the raw densities and SH coefficients of a
 float32 tree are fitted to target pixel colours with the NeRF loss (Sec. 3,
 eqn:nerfloss; here the mean over the batch and the colour channels) and plain
-SGD.  One step: forward render of a random ray batch (the first pass of the
-App. B.3 scheme), loss gradient, backward replay with atomics (second pass),
-SGD update that also clears the gradients -- four library kernels.  torch
-only holds the buffers and draws the batch indices.
+SGD.  One step: forward render of a random ray batch that keeps its pieces
+(the first pass of the App. B.3 scheme), loss gradient, backward replay with
+atomics over the same pieces (second pass), SGD updates that also clear the
+gradients -- library calls only.  torch holds the buffers and draws the
+batch indices.
 """
 from __future__ import annotations
 
@@ -41,6 +42,7 @@ class Trainer:
         self.rgb = torch.empty((batch, 3), **f)
         self.grad_rgb = torch.empty((batch, 3), **f)
         self.sq = torch.zeros(1, **f)
+        self.slot = torch.empty(batch, dtype=torch.int32, device=dev)
         self.g_sigma = torch.zeros_like(tree.sigma)
         self.g_sh = torch.zeros_like(tree.sh)
         self.opts = make_opts(bg, stop_T)
@@ -63,13 +65,14 @@ class Trainer:
             torch.index_select(self.d, 0, idx, out=self.bd)
             torch.index_select(self.t, 0, idx, out=self.bt)
             self.sq.zero_()
-            L.call("po_render_rays", tr.handle, n, self.bo.data_ptr(), self.bd.data_ptr(), ctypes.byref(self.opts),
-                   self.rgb.data_ptr(), None, s)
+            # the render keeps its pieces for the backward (App. B.3's two passes)
+            L.call("po_render_rays_keep", tr.handle, n, self.bo.data_ptr(), self.bd.data_ptr(),
+                   ctypes.byref(self.opts), self.rgb.data_ptr(), self.slot.data_ptr(), s)
             L.call("po_mse_grad", n, self.rgb.data_ptr(), self.bt.data_ptr(), ctypes.c_float(1.0 / (3 * n)),
                    self.grad_rgb.data_ptr(), self.sq.data_ptr(), s)
-            L.call("po_render_rays_backward", tr.handle, n, self.bo.data_ptr(), self.bd.data_ptr(),
+            L.call("po_render_rays_backward_kept", tr.handle, n, self.bo.data_ptr(), self.bd.data_ptr(),
                    ctypes.byref(self.opts), self.rgb.data_ptr(), self.grad_rgb.data_ptr(), self.g_sigma.data_ptr(),
-                   self.g_sh.data_ptr(), s)
+                   self.g_sh.data_ptr(), self.slot.data_ptr(), s)
             L.call("po_sgd_step", tr.sigma.numel(), tr.sigma.data_ptr(), self.g_sigma.data_ptr(),
                    ctypes.c_float(self.lr_sigma), 1, s)
             L.call("po_sgd_step", tr.sh.numel(), tr.sh.data_ptr(), self.g_sh.data_ptr(),

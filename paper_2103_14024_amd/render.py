@@ -188,6 +188,56 @@ def render_rays_backward(tree, origins, dirs, rgb_fwd, grad_rgb, bg=(1.0, 1.0, 1
     return grad_sigma, grad_sh
 
 
+def _slots(t, n):
+    torch = _torch()
+    if not (t.is_cuda and t.dtype == torch.int32 and tuple(t.shape) == (n,) and t.is_contiguous()):
+        raise ValueError(f"ray_slot must be a contiguous int32 device tensor of shape ({n},)")
+    return t
+
+
+def render_rays_keep(tree, origins, dirs, ray_slot, bg=(1.0, 1.0, 1.0), stop_T=1e-4, max_steps=0, out=None,
+                     stream=None, one_pass=False):
+    """render_rays (float32 tree, no aux or viewer options) that keeps its
+    pieces in the stream's work queue for render_rays_backward_kept;
+    ray_slot: (n,) int32 device tensor the library overwrites."""
+    torch = _torch()
+    _rays3(origins, "origins")
+    _rays3(dirs, "dirs")
+    n = origins.shape[0]
+    if dirs.shape[0] != n:
+        raise ValueError("origins and dirs differ in length")
+    _slots(ray_slot, n)
+    rgb = _out(out, (n, 3), "out") if out is not None else torch.empty((n, 3), dtype=torch.float32,
+                                                                       device=origins.device)
+    opts = make_opts(bg, stop_T, max_steps, one_pass=one_pass)
+    L.call("po_render_rays_keep", tree.handle, n, origins.data_ptr(), dirs.data_ptr(), ctypes.byref(opts),
+           rgb.data_ptr(), ray_slot.data_ptr(), _stream_ptr(stream))
+    return rgb
+
+
+def render_rays_backward_kept(tree, origins, dirs, rgb_fwd, grad_rgb, ray_slot, grad_sigma, grad_sh,
+                              bg=(1.0, 1.0, 1.0), stop_T=1e-4, max_steps=0, stream=None, one_pass=False):
+    """render_rays_backward of the rays of the last render_rays_keep on the
+    same stream (same tree, tensors and options), reusing its pieces;
+    accumulates into grad_sigma (n_leaves,) and grad_sh (n_leaves, stride)."""
+    _rays3(origins, "origins")
+    _rays3(dirs, "dirs")
+    _rays3(rgb_fwd, "rgb_fwd")
+    _rays3(grad_rgb, "grad_rgb")
+    n = origins.shape[0]
+    for t, name in ((dirs, "dirs"), (rgb_fwd, "rgb_fwd"), (grad_rgb, "grad_rgb")):
+        if t.shape[0] != n:
+            raise ValueError(f"{name} has {t.shape[0]} rows, origins {n}")
+    _slots(ray_slot, n)
+    _out(grad_sigma, (tree.n_leaves,), "grad_sigma")
+    _out(grad_sh, (tree.n_leaves, tree.stride), "grad_sh")
+    opts = make_opts(bg, stop_T, max_steps, one_pass=one_pass)
+    L.call("po_render_rays_backward_kept", tree.handle, n, origins.data_ptr(), dirs.data_ptr(), ctypes.byref(opts),
+           rgb_fwd.data_ptr(), grad_rgb.data_ptr(), grad_sigma.data_ptr(), grad_sh.data_ptr(), ray_slot.data_ptr(),
+           _stream_ptr(stream))
+    return grad_sigma, grad_sh
+
+
 class RenderRaysFn:
     """torch.autograd.Function over (sigma, sh) of a float32 tree.
 

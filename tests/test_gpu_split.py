@@ -379,10 +379,17 @@ def test_split_backward(po, fog, scene, gamma):
     for a, b in ((0, h), (h, len(o))):
         po.render_rays_backward(tree, og[a:b], dg[a:b], rgb1[a:b], gg[a:b], bg=bg, stop_T=gamma, grad_sigma=hs,
                                 grad_sh=hsh)
+    # the kept render and the backward over its own pieces
+    slot = torch.empty(len(o), dtype=torch.int32, device="cuda")
+    rgbk = po.render_rays_keep(tree, og, dg, slot, bg=bg, stop_T=gamma)
+    ks, ksh = torch.zeros_like(gs), torch.zeros_like(gsh)
+    po.render_rays_backward_kept(tree, og, dg, rgbk, gg, slot, ks, ksh, bg=bg, stop_T=gamma)
     torch.cuda.synchronize()
+    assert float((rgbk - rgb).abs().max()) <= 1e-6
+    assert int((slot >= 0).sum()) > 0
     (ls, hs_), (lh, hh), n_str = gradcheck.grad_envelope(ot, o, d, g, bg, gamma)
     _say(f"{scene} {gamma}: {n_str} of {len(o)} rays straddle stop_T")
-    for path, (x, y) in (("split", (gs, gsh)), ("one pass", (hs, hsh))):
+    for path, (x, y) in (("split", (gs, gsh)), ("one pass", (hs, hsh)), ("kept", (ks, ksh))):
         a, b = gradcheck.to_cells(tree, x.cpu().numpy(), y.cpu().numpy())
         gradcheck.check(a, ls, hs_, f"{scene} {gamma} {path} dsigma")
         gradcheck.check(b, lh, hh, f"{scene} {gamma} {path} dsh")
@@ -420,14 +427,58 @@ def test_split_backward_training_shape(po):
     rgb = po.render_rays(tree, og, dg, stop_T=1e-4)
     gg = (2.0 / rgb.numel()) * (rgb - target)
     gs, gsh = po.render_rays_backward(tree, og, dg, rgb, gg.contiguous(), stop_T=1e-4)
+    # the training step's path: the kept render and the backward over its pieces
+    slot = torch.empty(65536, dtype=torch.int32, device="cuda")
+    rgbk = po.render_rays_keep(tree, og, dg, slot, stop_T=1e-4)
+    ks, ksh = torch.zeros_like(gs), torch.zeros_like(gsh)
+    po.render_rays_backward_kept(tree, og, dg, rgbk, gg.contiguous(), slot, ks, ksh, stop_T=1e-4)
     torch.cuda.synchronize()
+    assert float((rgbk - rgb).abs().max()) <= 1e-6
     g = gg.cpu().numpy().astype(np.float64)
     ot = oracle.OracleTree(gt["depth"], gt["sh_degree"], gt["center"], gt["half"], gt["cells"], sig, sh)
     (ls, hs_), (lh, hh), n_str = gradcheck.grad_envelope(ot, o, d, g, (1.0, 1.0, 1.0), 1e-4)
     _say(f"training shape: {n_str} straddling rays")
-    a, b = gradcheck.to_cells(tree, gs.cpu().numpy(), gsh.cpu().numpy())
-    gradcheck.check(a, ls, hs_, "training shape dsigma")
-    gradcheck.check(b, lh, hh, "training shape dsh")
+    for path, (x, y) in (("split", (gs, gsh)), ("kept", (ks, ksh))):
+        a, b = gradcheck.to_cells(tree, x.cpu().numpy(), y.cpu().numpy())
+        gradcheck.check(a, ls, hs_, f"training shape {path} dsigma")
+        gradcheck.check(b, lh, hh, f"training shape {path} dsh")
+    assert po.device_errors() == 0
+
+
+def test_kept_backward_refusals(po, fog):
+    # the backward over kept pieces runs only right after the kept render of
+    # the same rays and options on the same stream, and only once
+    import torch
+
+    from paper_2103_14024_amd._lib import PlenOctreeError
+
+    s, tree, ot = fog
+    o, d = scenes.random_rays(70000, 53, radius=2.5, spread=0.9)
+    og, dg = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (o, d))
+    gg = torch.full((len(o), 3), 1e-3, device="cuda")
+    slot = torch.empty(len(o), dtype=torch.int32, device="cuda")
+    gs = torch.zeros((tree.n_leaves,), device="cuda")
+    gsh = torch.zeros((tree.n_leaves, tree.stride), device="cuda")
+    rgb = po.render_rays_keep(tree, og, dg, slot)
+    po.render_rays(tree, og, dg)  # a split render on the same stream's queue
+    with pytest.raises(PlenOctreeError):
+        po.render_rays_backward_kept(tree, og, dg, rgb, gg, slot, gs, gsh)
+    rgb = po.render_rays_keep(tree, og, dg, slot)
+    with pytest.raises(PlenOctreeError):
+        po.render_rays_backward_kept(tree, og, dg, rgb, gg, slot, gs, gsh, stop_T=1e-2)
+    po.render_rays_backward_kept(tree, og, dg, rgb, gg, slot, gs, gsh)
+    with pytest.raises(PlenOctreeError):
+        po.render_rays_backward_kept(tree, og, dg, rgb, gg, slot, gs, gsh)  # consumed
+    with pytest.raises(ValueError):
+        po.render_rays_keep(tree, og, dg, slot[:100])
+    # below 65536 rays both run in one pass: the same gradient as the plain backward
+    n = 5000
+    rgb_s = po.render_rays_keep(tree, og[:n], dg[:n], slot[:n])
+    ks, ksh = torch.zeros_like(gs), torch.zeros_like(gsh)
+    po.render_rays_backward_kept(tree, og[:n], dg[:n], rgb_s, gg[:n], slot[:n], ks, ksh)
+    ps, psh = po.render_rays_backward(tree, og[:n], dg[:n], rgb_s, gg[:n])
+    torch.cuda.synchronize()
+    assert torch.allclose(ks, ps, rtol=1e-5, atol=1e-9) and torch.allclose(ksh, psh, rtol=1e-5, atol=1e-9)
     assert po.device_errors() == 0
 
 
