@@ -132,11 +132,14 @@ inline int po_camera_split_steps(int64_t waves) {
 #ifndef PO_RAYS_SMALL
 #define PO_RAYS_SMALL (1 << 18)
 #endif
+#ifndef PO_RAYS_SPLIT_STEPS
+#define PO_RAYS_SPLIT_STEPS 4
+#endif
 #ifndef PO_RAYS_CHUNK_STEPS
-#define PO_RAYS_CHUNK_STEPS 12
+#define PO_RAYS_CHUNK_STEPS 6
 #endif
 #ifndef PO_RAYS_CHUNK_CAP
-#define PO_RAYS_CHUNK_CAP 16
+#define PO_RAYS_CHUNK_CAP 12
 #endif
 struct KSplit {
     int32_t* count;        // [kSplitRegions] chunk slots claimed (may exceed the region); count2 follows
@@ -164,8 +167,13 @@ struct KSplit {
 // backward of the same rays cut them alike: the transmittance in front of
 // every piece is then the same float product in both, so the backward stops
 // on the sample where the render that produced its colour stopped.
+// (Training step, 65,536 random rays of the depth-8 tree, forward and
+// backward over the same pieces: 0.558 ms with a 28-cell first walk and
+// 8-cell pieces (cap 16), 0.460 ms with a 4-cell first walk and 6-cell
+// pieces (cap 12).)
 inline void po_rays_piece_sizes(int64_t n, KSplit* S) {
     if (n < PO_RAYS_SMALL) {
+        S->split_steps = PO_RAYS_SPLIT_STEPS;
         S->chunk_steps = PO_RAYS_CHUNK_STEPS;
         S->sub_steps = PO_RAYS_CHUNK_STEPS;
         S->chunk_cap = PO_RAYS_CHUNK_CAP;

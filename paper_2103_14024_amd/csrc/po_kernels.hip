@@ -2441,9 +2441,10 @@ hipError_t po_launch_rays_split(const po_tree* t, int64_t n, const float* o, con
     S.ray_o = o;
     S.ray_d = d;
     S.n_rays = n;
-    // a batch of rays below a frame's size fills the chip less: smaller pieces
-    // (65536 random rays of the depth-8 training tree: 203 us with 8-cell
-    // pieces, 325 us with the frame's 32, 300 us in one pass)
+    // a batch of rays below a frame's size fills the chip less: a shorter
+    // first walk and smaller pieces (65536 random rays of the depth-8
+    // training tree: 203 us with 8-cell pieces, 325 us with the frame's 32,
+    // 300 us in one pass)
     po_rays_piece_sizes(n, &S);
     const int n_blocks = (int)((n + kBlock - 1) / kBlock);
     const int variant = po_fwd_variant(op, aux, t->kt);
