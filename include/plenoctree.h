@@ -369,6 +369,15 @@ po_status po_render_rays_backward_kept(const po_tree* t, int64_t n, const float*
 po_status po_mse_grad(int64_t n, const float* d_rgb, const float* d_target, float scale, float* d_grad_rgb,
                       float* d_sq_sum, void* stream);
 po_status po_sgd_step(int64_t n, float* d_param, float* d_grad, float lr, int32_t zero_grad, void* stream);
+/* po_gather_rays: the rows of a training batch (Sec. 4.3: random rays of the
+ * training images), for i < n: d_bo[i] = d_o[d_idx[i]], d_bd[i] =
+ * d_d[d_idx[i]] and d_bt[i] = d_t[d_idx[i]] (rows of 3 floats; d_idx int64
+ * device indices, each in [0, n_src)).  The indices are checked on the
+ * device: an index outside [0, n_src) gathers zeros and is counted by
+ * po_device_errors.  Errors: PO_ERR_INVALID (NULL arrays with n > 0, n < 0,
+ * n_src < 1), PO_ERR_DEVICE. */
+po_status po_gather_rays(int64_t n, const int64_t* d_idx, int64_t n_src, const float* d_o, const float* d_d,
+                         const float* d_t, float* d_bo, float* d_bd, float* d_bt, void* stream);
 
 /* ---------------------------------------------------------------- batches
  * One job renders the 16x16 tiles [tile_begin, tile_end) of one camera

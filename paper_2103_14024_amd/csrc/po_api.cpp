@@ -933,6 +933,17 @@ po_status po_sgd_step(int64_t n, float* d_param, float* d_grad, float lr, int32_
     return ok();
 }
 
+po_status po_gather_rays(int64_t n, const int64_t* d_idx, int64_t n_src, const float* d_o, const float* d_d,
+                         const float* d_t, float* d_bo, float* d_bd, float* d_bt, void* stream) {
+    if (n < 0 || n >= (1ll << 40)) return fail(PO_ERR_INVALID, "n = %lld out of range", (long long)n);
+    if (n_src < 1 || n_src >= (1ll << 40)) return fail(PO_ERR_INVALID, "n_src = %lld out of range", (long long)n_src);
+    if (n == 0) return ok();
+    if (!d_idx || !d_o || !d_d || !d_t || !d_bo || !d_bd || !d_bt) return fail(PO_ERR_INVALID, "NULL array");
+    hipError_t e = po_launch_gather_rays(n, d_idx, n_src, d_o, d_d, d_t, d_bo, d_bd, d_bt, (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "gather_rays launch");
+    return ok();
+}
+
 po_status po_camera_tiles(const po_camera* cam, int32_t* n_tiles) {
     if (po_status s = check_camera(cam)) return s;
     if (!n_tiles) return fail(PO_ERR_INVALID, "n_tiles is NULL");

@@ -1987,12 +1987,15 @@ __global__ __launch_bounds__(kBlock) void k_traversal_stats(KTree tr, KCam cam, 
 // Loss gradient of the NeRF loss (Sec. 3, eqn:nerfloss) for one batch: one
 // thread per ray; squared errors are summed within the wave and added once
 // per wave.
+// Grid-stride over the rays; the squared errors are summed per workgroup
+// (waves, then LDS) and added with one float atomic per workgroup: one
+// atomic per wave on the single sum address serialised in L2 (15 us for
+// 65536 rays).
 __global__ __launch_bounds__(256) void k_mse_grad(int64_t n, const float* __restrict__ rgb,
                                                   const float* __restrict__ target, float scale,
                                                   float* __restrict__ grad, float* __restrict__ sq_sum) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     float e2 = 0.0f;
-    if (i < n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float e = rgb[3 * i + c] - target[3 * i + c];
@@ -2001,7 +2004,31 @@ __global__ __launch_bounds__(256) void k_mse_grad(int64_t n, const float* __rest
         }
     }
     for (int off = 32; off > 0; off >>= 1) e2 += __shfl_xor(e2, off, 64);
-    if ((threadIdx.x & 63) == 0 && e2 != 0.0f) atomicAdd(sq_sum, e2);
+    __shared__ float part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = e2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float t = (part[0] + part[1]) + (part[2] + part[3]);
+        if (t != 0.0f) atomicAdd(sq_sum, t);
+    }
+}
+
+// Batch rows of a training step: three rows of 3 floats per ray.
+__global__ __launch_bounds__(256) void k_gather_rays(int64_t n, const int64_t* __restrict__ idx, int64_t n_src,
+                                                     const float* __restrict__ o, const float* __restrict__ d,
+                                                     const float* __restrict__ t, float* __restrict__ bo,
+                                                     float* __restrict__ bd, float* __restrict__ bt) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = idx[i];
+    const bool ok = (j >= 0) & (j < n_src);
+    if (!ok) atomicAdd(&g_po_errors, 1ull);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        bo[3 * i + c] = ok ? o[3 * j + c] : 0.0f;
+        bd[3 * i + c] = ok ? d[3 * j + c] : 0.0f;
+        bt[3 * i + c] = ok ? t[3 * j + c] : 0.0f;
+    }
 }
 
 // Plain SGD on the leaf values (Sec. 4.3): p -= lr g, optionally clearing g.
@@ -2514,8 +2541,16 @@ hipError_t po_launch_camera_rays(const KCam& cam, float* o, float* d, hipStream_
 
 hipError_t po_launch_mse_grad(int64_t n, const float* rgb, const float* target, float scale, float* grad,
                               float* sq_sum, hipStream_t s) {
-    hipLaunchKernelGGL(k_mse_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, rgb, target, scale, grad,
-                       sq_sum);
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_mse_grad, dim3((unsigned)(blocks < 512 ? blocks : 512)), dim3(256), 0, s, n, rgb, target,
+                       scale, grad, sq_sum);
+    return hipGetLastError();
+}
+
+hipError_t po_launch_gather_rays(int64_t n, const int64_t* idx, int64_t n_src, const float* o, const float* d,
+                                 const float* t, float* bo, float* bd, float* bt, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_rays, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, idx, n_src, o, d, t,
+                       bo, bd, bt);
     return hipGetLastError();
 }
 

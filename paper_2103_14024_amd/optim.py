@@ -61,9 +61,8 @@ class Trainer:
         tr = self.tree
         with torch.cuda.stream(ts):
             idx = torch.randint(0, self.o.shape[0], (n,), device=self.o.device, generator=self.gen)
-            torch.index_select(self.o, 0, idx, out=self.bo)
-            torch.index_select(self.d, 0, idx, out=self.bd)
-            torch.index_select(self.t, 0, idx, out=self.bt)
+            L.call("po_gather_rays", n, idx.data_ptr(), self.o.shape[0], self.o.data_ptr(), self.d.data_ptr(),
+                   self.t.data_ptr(), self.bo.data_ptr(), self.bd.data_ptr(), self.bt.data_ptr(), s)
             self.sq.zero_()
             # the render keeps its pieces for the backward (App. B.3's two passes)
             L.call("po_render_rays_keep", tr.handle, n, self.bo.data_ptr(), self.bd.data_ptr(),

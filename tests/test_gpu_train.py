@@ -62,6 +62,48 @@ def test_loss_grad_and_sgd_kernels(po):
     assert torch.allclose(p, want, rtol=1e-6, atol=1e-7) and gp.abs().max().item() == 0.0
 
 
+def test_loss_grad_large_and_gather(po):
+    # the loss gradient over more rays than one grid pass covers (grid-stride
+    # loop, one atomic per workgroup) and the batch gather against its
+    # definition, including an out-of-range index (zeros, counted)
+    import ctypes
+
+    import torch
+
+    from paper_2103_14024_amd import _lib as L
+
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    n = 400_003
+    rgb = torch.rand((n, 3), device="cuda", generator=g)
+    tgt = torch.rand((n, 3), device="cuda", generator=g)
+    grad = torch.empty_like(rgb)
+    sq = torch.zeros(1, device="cuda")
+    L.call("po_mse_grad", n, rgb.data_ptr(), tgt.data_ptr(), ctypes.c_float(1.0 / (3 * n)), grad.data_ptr(),
+           sq.data_ptr(), s)
+    e = (rgb - tgt).double()
+    assert torch.allclose(grad.double(), 2 * e / (3 * n), rtol=1e-6, atol=1e-14)
+    assert abs(sq.item() - float((e ** 2).sum())) < 1e-5 * float((e ** 2).sum())
+    m, k = 50_000, 7001
+    o, d, t = (torch.rand((m, 3), device="cuda", generator=g) for _ in range(3))
+    idx = torch.randint(0, m, (k,), device="cuda", generator=g)
+    idx[5] = m  # out of range
+    bo, bd, bt = (torch.full((k, 3), 7.0, device="cuda") for _ in range(3))
+    po.reset_device_errors()
+    L.call("po_gather_rays", k, idx.data_ptr(), m, o.data_ptr(), d.data_ptr(), t.data_ptr(), bo.data_ptr(),
+           bd.data_ptr(), bt.data_ptr(), s)
+    ok = torch.ones(k, dtype=torch.bool, device="cuda")
+    ok[5] = False
+    for src, dst in ((o, bo), (d, bd), (t, bt)):
+        assert torch.equal(dst[ok], src[idx[ok]])
+        assert torch.equal(dst[5], torch.zeros(3, device="cuda"))
+    assert po.device_errors() == 1
+    po.reset_device_errors()
+    with pytest.raises(L.PlenOctreeError):
+        L.call("po_gather_rays", k, idx.data_ptr(), 0, o.data_ptr(), d.data_ptr(), t.data_ptr(), bo.data_ptr(),
+               bd.data_ptr(), bt.data_ptr(), s)
+
+
 def test_training_reduces_loss(po):
     gt = scenes.scene_blobs(depth=6, sh_degree=2, seed=4, data_seed=5)
     tgt_tree = po.Tree.from_scene(gt)
