@@ -1396,11 +1396,25 @@ __global__ __launch_bounds__(kBlock) void k_render_join(KBatch<1> B, KSplit S) {
     const int m = in.y >> 8;
     const ContHead hd = reinterpret_cast<const ContHead*>(S.head)[q];
     const KJob& J = B.job[0];
-    const PieceOut* part = reinterpret_cast<const PieceOut*>(S.part);
-    const PieceOut* part2 = reinterpret_cast<const PieceOut*>(S.part2);
+    PieceOut* part = reinterpret_cast<PieceOut*>(S.part);
+    PieceOut* part2 = reinterpret_cast<PieceOut*>(S.part2);
     const SubHead* head2 = reinterpret_cast<const SubHead*>(S.head2);
     const size_t p = (size_t)hd.pix;
+    // the join of a kept ray-list render also writes, over each piece's
+    // result, the transmittance and colour prefix in front of it and whether
+    // it lies before the early stop (Tlast 1) or not (-1): the prefixes its
+    // backward differentiates from (what k_piece_prefix computes otherwise)
+    bool keep = false;
+    if constexpr (SRC == 1 && V != PO_FWD_VIEW) keep = S.ray_slot != nullptr;
     JoinAcc A;
+    auto prefix = [&](PieceOut* rec, PieceOut o, bool past) {
+        o.c0 = A.c[0];
+        o.c1 = A.c[1];
+        o.c2 = A.c[2];
+        o.T = A.Tp;
+        o.Tlast = past ? -1.0f : 1.0f;
+        *rec = o;
+    };
     A.Tp = hd.T;
     A.c[0] = hd.c0;
     A.c[1] = hd.c1;
@@ -1417,19 +1431,22 @@ __global__ __launch_bounds__(kBlock) void k_render_join(KBatch<1> B, KSplit S) {
     const double end = walk_end<V, SRC>(J, S, hd.pix);
     bool done = false;
     int qj = q;
-    for (int j = 0; j < m && !done; ++j) {
+    for (int j = 0; j < m && (keep || !done); ++j) {
         const PieceOut o = part[qj];
         const int qo = qj;
         qj = S.info[qj].z;
-        done = join_piece<T, K, VEC, NL, V, SRC>(J, S, hd.pix, hd.s, end, j, m, o, S.view_part + qo, A);
-        if (o.n_sub > 0 && !done) {
+        if (keep) prefix(part + qo, o, done);
+        if (!done) done = join_piece<T, K, VEC, NL, V, SRC>(J, S, hd.pix, hd.s, end, j, m, o, S.view_part + qo, A);
+        if (o.n_sub > 0 && (keep || !done)) {
             // the remainder's sub-chunks (bounds read only to walk one again)
             double slo = 0.0, shi = 0.0;
             int qk = o.sub;
-            for (int k = 0; k < o.n_sub && !done; ++k) {
+            for (int k = 0; k < o.n_sub && (keep || !done); ++k) {
                 const PieceOut o2 = part2[qk];
                 const int qo2 = qk;
                 qk = S.info2[qk].z;
+                if (keep) prefix(part2 + qo2, o2, done);
+                if (done) continue;
                 if (o2.Tlast >= 0.0f && A.Tp * o2.Tlast < J.op.stop_T && shi == 0.0) {
                     const SubHead sh = head2[o.sub];
                     slo = sh.lo;
@@ -2261,9 +2278,10 @@ hipError_t backward_split_t(const po_tree* t, int64_t n, const float* o, const f
     return hipGetLastError();
 }
 
-// The backward of a kept render: its pieces and their forward results are in
-// the queue already, so the chunk and sub-chunk kernels are not run again
-// and the counters are not cleared.
+// The backward of a kept render: its pieces are in the queue already, and
+// its join wrote each piece's prefix over the piece's result, so neither
+// the chunk and sub-chunk kernels nor k_piece_prefix run again, and the
+// counters are not cleared.
 template <int K>
 hipError_t backward_kept_t(const po_tree* t, int64_t n, const float* o, const float* d, const KOpts& op,
                            const float* rgb_fwd, const float* grad, float* gsig, float* gsh, const KSplit& S0,
@@ -2279,19 +2297,14 @@ hipError_t backward_kept_t(const po_tree* t, int64_t n, const float* o, const fl
     S.ray_o = o;
     S.ray_d = d;
     S.n_rays = n;
-    dim3 g1((unsigned)grid_for(B.n_blocks)), g2((unsigned)(kSplitRegions * (S.region_slots / kBlock))),
-        g3(2u * g2.x), blk(kBlock);
+    dim3 g1((unsigned)grid_for(B.n_blocks)), g3(2u * (unsigned)(kSplitRegions * (S.region_slots / kBlock))),
+        blk(kBlock);
     const size_t lds = stack_bytes(t->kt.depth);
-    const bool sg = t->kt.lobes != nullptr;
     po_rays_piece_sizes(n, &S);
 #define PO_BKEPT(VEC_, NL_)                                                                                       \
     do {                                                                                                         \
         hipLaunchKernelGGL((k_backward_first_kept<K, VEC_, NL_>), g1, blk, lds, s, B, S, rgb_fwd, grad, gsig,    \
                            gsh);                                                                                 \
-        if (sg)                                                                                                  \
-            hipLaunchKernelGGL((k_piece_prefix<K, VEC_, NL_, PO_FWD_SG>), g2, blk, lds, s, B, S);                \
-        else                                                                                                     \
-            hipLaunchKernelGGL((k_piece_prefix<K, VEC_, NL_, PO_FWD_SH>), g2, blk, lds, s, B, S);                \
         hipLaunchKernelGGL((k_backward_pieces<K, VEC_, NL_>), g3, blk, lds, s, B, S, rgb_fwd, grad, gsig, gsh);  \
     } while (0)
     if (use_fast<float, K>(t))
