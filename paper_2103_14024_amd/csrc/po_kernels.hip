@@ -2249,13 +2249,14 @@ hipError_t backward_split_t(const po_tree* t, int64_t n, const float* o, const f
     S.ray_o = o;
     S.ray_d = d;
     S.n_rays = n;
+    // the pieces of the render of the same rays (before the grids: they
+    // cover the queue regions as this pass lays them out)
+    po_rays_piece_sizes(n, &S);
     hipLaunchKernelGGL(k_zero_i32, dim3(2), dim3(kSplitRegions), 0, s, S.count, 2 * kSplitRegions);
     dim3 g1((unsigned)grid_for(B.n_blocks)), g2((unsigned)(kSplitRegions * (S.region_slots / kBlock))),
         g3(2u * g2.x), blk(kBlock);
     const size_t lds = stack_bytes(t->kt.depth);
     const bool sg = t->kt.lobes != nullptr;
-    // the pieces of the render of the same rays
-    po_rays_piece_sizes(n, &S);
 #define PO_BSPLIT(VEC_, NL_)                                                                                    \
     do {                                                                                                       \
         hipLaunchKernelGGL((k_backward_split<K, VEC_, NL_>), g1, blk, lds, s, B, S, rgb_fwd, grad, gsig, gsh); \
@@ -2297,10 +2298,10 @@ hipError_t backward_kept_t(const po_tree* t, int64_t n, const float* o, const fl
     S.ray_o = o;
     S.ray_d = d;
     S.n_rays = n;
+    po_rays_piece_sizes(n, &S);
     dim3 g1((unsigned)grid_for(B.n_blocks)), g3(2u * (unsigned)(kSplitRegions * (S.region_slots / kBlock))),
         blk(kBlock);
     const size_t lds = stack_bytes(t->kt.depth);
-    po_rays_piece_sizes(n, &S);
 #define PO_BKEPT(VEC_, NL_)                                                                                       \
     do {                                                                                                         \
         hipLaunchKernelGGL((k_backward_first_kept<K, VEC_, NL_>), g1, blk, lds, s, B, S, rgb_fwd, grad, gsig,    \
