@@ -561,10 +561,16 @@ template <typename T, int K, int VEC, int NL, bool VIEW>
 struct FwdSampler {
     static constexpr int NW = Words<T, NL>::N;
     static constexpr bool kClip = VIEW;
+    // float16 records: the basis values live in LDS ([k][lane], written by
+    // init_basis) instead of K registers, which takes the float16 chunk and
+    // sub-chunk walks to 5 waves per SIMD (depth-9 800x800 frame 0.461 ->
+    // 0.451 ms, 1920x1080 1.13 -> 1.06 ms)
+    static constexpr bool kLdsY = std::is_same<T, __half>::value && !VIEW;
     __amdgpu_buffer_rsrc_t sig, shb;
     uint32_t sig_end, sh_end, rec_bytes;
     float stopT;
-    float Y[K];
+    float Y[kLdsY ? 1 : K];
+    float* Yl;  // kLdsY: this lane's column of the LDS basis values
     float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, Tl = 1.0f;
     float dep = 0.0f;
     int ns = 0;
@@ -586,9 +592,18 @@ struct FwdSampler {
         if (!(s > 0.0f)) return false;
         const float ex = __expf(-(s * delta));
         const float wgt = Tl * (1.0f - ex);
-        c0 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, 0, Y)), c0);
-        c1 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, K, Y)), c1);
-        c2 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, 2 * K, Y)), c2);
+        if constexpr (kLdsY) {
+            float Yv[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) Yv[k] = Yl[k * kBlock];
+            c0 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, 0, Yv)), c0);
+            c1 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, K, Yv)), c1);
+            c2 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, 2 * K, Yv)), c2);
+        } else {
+            c0 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, 0, Y)), c0);
+            c1 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, K, Y)), c1);
+            c2 = fmaf(wgt, sigmoid(dot_channel<T, K>(w, 2 * K, Y)), c2);
+        }
         if constexpr (VIEW) {
             // integral of t sigma T(t) over the segment [ta, ta + delta]:
             // Tl (ta alpha + delta f), f = alpha / tau - e^-tau, from its
@@ -604,6 +619,28 @@ struct FwdSampler {
         return Tl < stopT;
     }
 };
+
+// The SH or SG basis at the ray direction (once per ray) for a plain
+// forward sampler: into its registers, or for float16 records into this
+// lane's column of an LDS array (one per kernel, K x kBlock floats).
+template <typename T, int K, int V, class Smp>
+__device__ __forceinline__ void init_basis(Smp& smp, const KTree& tr, const Ray& r) {
+    if constexpr (Smp::kLdsY) {
+        __shared__ float s_Y[K * kBlock];
+        float Yt[K];
+        if constexpr (V == PO_FWD_SG)
+            sg_basis<K>(tr.lobes, r.dn[0], r.dn[1], r.dn[2], Yt);
+        else
+            sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], Yt);
+        smp.Yl = s_Y + threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < K; ++k) smp.Yl[k * kBlock] = Yt[k];
+    } else if constexpr (V == PO_FWD_SG) {
+        sg_basis<K>(tr.lobes, r.dn[0], r.dn[1], r.dn[2], smp.Y);
+    } else {
+        sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], smp.Y);
+    }
+}
 
 // Codebook leaves (App. B.2): the record holds one 16-bit codebook position
 // per basis function; consume() gathers the K float16 colours (8 bytes each,
@@ -745,10 +782,10 @@ __device__ __forceinline__ void render_one(const KTree& tr, const KOpts& op, con
             smp.cb_basis_bytes = (uint32_t)tr.cb_entries * 8u;
             smp.cb = raw_rsrc(tr.codebook, (uint32_t)K * smp.cb_basis_bytes);
         }
-        if constexpr (V == PO_FWD_SH || V == PO_FWD_CB)
+        if constexpr (V == PO_FWD_SH || V == PO_FWD_SG)
+            init_basis<T, K, V>(smp, tr, r);
+        else if constexpr (V == PO_FWD_CB)
             sh_basis<K>(r.dn[0], r.dn[1], r.dn[2], smp.Y);
-        else if constexpr (V == PO_FWD_SG)
-            sg_basis<K>(tr.lobes, r.dn[0], r.dn[1], r.dn[2], smp.Y);
         else
             colour_basis<K>(tr, r.dn[0], r.dn[1], r.dn[2], smp.Y);
         if constexpr (VIEW) {
@@ -979,8 +1016,8 @@ __device__ __forceinline__ void fwd_init(Smp& smp, const KTree& tr, const KOpts&
         smp.cb_basis_bytes = (uint32_t)tr.cb_entries * 8u;
         smp.cb = raw_rsrc(tr.codebook, (uint32_t)K * smp.cb_basis_bytes);
     }
-    if constexpr (V == PO_FWD_SG) {
-        sg_basis<K>(tr.lobes, r.dn[0], r.dn[1], r.dn[2], smp.Y);
+    if constexpr (V == PO_FWD_SH || V == PO_FWD_SG) {
+        init_basis<T, K, V>(smp, tr, r);
     } else if constexpr (V == PO_FWD_VIEW) {
         colour_basis<K>(tr, r.dn[0], r.dn[1], r.dn[2], smp.Y);
 #pragma unroll
@@ -1220,11 +1257,15 @@ __device__ __forceinline__ int split_slot(const int32_t* count, int region_slots
 // The plain (SH, SG) chunk and sub-chunk walks of records up to 192 bytes
 // are held to 128 VGPRs (4 waves per SIMD; unconstrained the float32 K=16
 // chunk kernel takes 131 and 3 waves): 0.639 against 0.671 ms per depth-9
-// 800x800 frame.  Larger records and the viewer and codebook variants would
-// spill (K=25 float32: 180 bytes of scratch, half the frame rate), so they
-// keep their natural count.
+// 800x800 frame; float16 SH records of K <= 16 with the basis values in
+// LDS, to 96 VGPRs (5 waves; 20 bytes of scratch outside the loop).  Larger
+// records and the viewer and codebook variants would spill (K=25 float32:
+// 180 bytes of scratch, half the frame rate; float16 K=25 at 5 waves: 144),
+// so they keep 4 waves or their natural count.
 template <typename T, int K, int V>
-constexpr int kPieceWaves = (V == PO_FWD_SH || V == PO_FWD_SG) && sizeof(T) * 3 * K <= 192 ? 4 : 1;
+constexpr int kPieceWaves = (V == PO_FWD_SH || V == PO_FWD_SG) && sizeof(T) * 3 * K <= 192
+                                ? (sizeof(T) == 2 && V == PO_FWD_SH && K <= 16 ? 5 : 4)
+                                : 1;
 
 template <typename T, int K, int VEC, int NL, int V, int SRC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kPieceWaves<T, K, V>, 8))) void k_render_chunks(
