@@ -445,6 +445,36 @@ def test_split_backward_training_shape(po):
     assert po.device_errors() == 0
 
 
+@pytest.mark.parametrize("deg", [1, 4])
+def test_kept_backward_sg(po, deg):
+    # the kept render and its backward over spherical-Gaussian leaves (K = 4
+    # and 25) against the FP64 oracle gradient, 70000 rays of the depth-6
+    # blob band (the render splits them)
+    import torch
+
+    K = (deg + 1) ** 2
+    s = scenes.scene_blobs(depth=6, sh_degree=deg, seed=12, data_seed=13)
+    s = dict(s, lobes=scenes.sg_lobes(K, 47))
+    tree = po.Tree.from_scene(s)
+    ot = oracle.OracleTree(s["depth"], deg, s["center"], s["half"], s["cells"], s["sigma"], s["sh"], lobes=s["lobes"])
+    o, d = scenes.random_rays(70000, 59, radius=2.0, spread=0.8)
+    g = np.random.default_rng(61).standard_normal((len(o), 3)).astype(np.float32)
+    og, dg, gg = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (o, d, g))
+    _say(f"kept backward, SG K={K}")
+    slot = torch.empty(len(o), dtype=torch.int32, device="cuda")
+    rgb = po.render_rays_keep(tree, og, dg, slot, stop_T=1e-4)
+    ks = torch.zeros((tree.n_leaves,), device="cuda")
+    ksh = torch.zeros((tree.n_leaves, tree.stride), device="cuda")
+    po.render_rays_backward_kept(tree, og, dg, rgb, gg, slot, ks, ksh, stop_T=1e-4)
+    torch.cuda.synchronize()
+    assert int((slot >= 0).sum()) > 1000
+    (ls, hs_), (lh, hh), n_str = gradcheck.grad_envelope(ot, o, d, g, (1.0, 1.0, 1.0), 1e-4)
+    a, b = gradcheck.to_cells(tree, ks.cpu().numpy(), ksh.cpu().numpy())
+    gradcheck.check(a, ls, hs_, f"SG K={K} kept dsigma")
+    gradcheck.check(b, lh, hh, f"SG K={K} kept dsh")
+    assert po.device_errors() == 0
+
+
 def test_kept_backward_refusals(po, fog):
     # the backward over kept pieces runs only right after the kept render of
     # the same rays and options on the same stream, and only once
