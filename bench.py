@@ -572,8 +572,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the renderer needs no communication and this build runs on a "
-              "single MI355X; rerun with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only (a render needs no communication between GPUs; several GPUs "
+              "would each render their own frames or requests); rerun with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
