@@ -243,7 +243,11 @@ class RenderRaysFn:
 
     Forward renders the rays (the first pass of App. B.3's Remark, storing the
     full colour C); backward replays the walk and accumulates the leaf
-    gradients with atomics (the second pass)."""
+    gradients with atomics (the second pass).  The forward keeps its pieces
+    (render_rays_keep), and the backward differentiates over them when they
+    are still valid (no other split work on the stream in between, first
+    backward of this forward), else it walks the rays again
+    (render_rays_backward): both give the gradient of the same colours."""
 
     _fn = None
 
@@ -257,16 +261,36 @@ class RenderRaysFn:
                 def forward(ctx, sigma, sh, tree, origins, dirs, bg, stop_T):
                     if sigma.data_ptr() != tree.sigma.data_ptr() or sh.data_ptr() != tree.sh.data_ptr():
                         raise ValueError("sigma/sh must be the tensors the tree is bound to")
-                    rgb = render_rays(tree, origins, dirs, bg=bg, stop_T=stop_T)
-                    ctx.tree, ctx.bg, ctx.stop_T = tree, bg, stop_T
-                    ctx.save_for_backward(origins, dirs, rgb)
+                    if tree.dtype == L.PO_F32:
+                        slot = torch.empty(origins.shape[0], dtype=torch.int32, device=origins.device)
+                        rgb = render_rays_keep(tree, origins, dirs, slot, bg=bg, stop_T=stop_T)
+                    else:
+                        # float16 and codebook trees render; their backward is refused
+                        slot = None
+                        rgb = render_rays(tree, origins, dirs, bg=bg, stop_T=stop_T)
+                    ctx.tree, ctx.bg, ctx.stop_T, ctx.kept = tree, bg, stop_T, slot is not None
+                    ctx.save_for_backward(origins, dirs, rgb, slot)
                     return rgb
 
                 @staticmethod
                 def backward(ctx, grad_rgb):
-                    origins, dirs, rgb = ctx.saved_tensors
-                    gs, gh = render_rays_backward(ctx.tree, origins, dirs, rgb, grad_rgb.contiguous(), bg=ctx.bg,
-                                                  stop_T=ctx.stop_T)
+                    origins, dirs, rgb, slot = ctx.saved_tensors
+                    g = grad_rgb.contiguous()
+                    tr = ctx.tree
+                    gs = torch.zeros((tr.n_leaves,), dtype=torch.float32, device=origins.device)
+                    gh = torch.zeros((tr.n_leaves, tr.stride), dtype=torch.float32, device=origins.device)
+                    kept = ctx.kept
+                    if kept:
+                        try:
+                            render_rays_backward_kept(tr, origins, dirs, rgb, g, slot, gs, gh, bg=ctx.bg,
+                                                      stop_T=ctx.stop_T)
+                        except L.PlenOctreeError as e:
+                            if e.status != L.PO_ERR_INVALID:
+                                raise
+                            kept = False  # the kept pieces are gone: walk the rays again
+                    if not kept:
+                        render_rays_backward(tr, origins, dirs, rgb, g, bg=ctx.bg, stop_T=ctx.stop_T,
+                                             grad_sigma=gs, grad_sh=gh)
                     return gs, gh, None, None, None, None, None
 
             cls._fn = _F
@@ -274,8 +298,8 @@ class RenderRaysFn:
 
 
 def render_rays_differentiable(tree, origins, dirs, bg=(1.0, 1.0, 1.0), stop_T=1e-4):
-    """Differentiable render: gradients flow to tree.sigma and tree.sh
-    (set requires_grad on them first)."""
+    """Differentiable render of a float32 tree: gradients flow to tree.sigma
+    and tree.sh (set requires_grad on them first)."""
     return RenderRaysFn.get().apply(tree.sigma, tree.sh, tree, origins, dirs, tuple(bg), float(stop_T))
 
 

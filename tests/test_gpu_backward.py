@@ -123,6 +123,28 @@ def test_autograd_function(po):
     assert tree.sh.grad[:, 27:].abs().max().item() == 0.0
 
 
+def test_autograd_function_f16_forward(po):
+    # a float16 tree renders through the autograd function (no kept pieces);
+    # asking for its gradient is refused, as the leaf gradients are float32 only
+    import torch
+
+    s = _scene(5, 2, 41)
+    tree = po.Tree.from_scene(s, dtype="f16")
+    o, d = scenes.random_rays(2048, 7, spread=1.0)
+    og, dg = _dev(o), _dev(d)
+    rgb = po.render_rays_differentiable(tree, og, dg, stop_T=1e-4)
+    ref = po.render_rays(tree, og, dg, stop_T=1e-4)
+    assert torch.equal(rgb, ref)
+    tree.sh.requires_grad_(True)
+    try:
+        rgb = po.render_rays_differentiable(tree, og, dg, stop_T=1e-4)
+        with pytest.raises(po.PlenOctreeError):
+            rgb.sum().backward()
+    finally:
+        tree.sh.requires_grad_(False)
+        tree.sh.grad = None
+
+
 def test_backward_rejects_mis_sized_buffers(po):
     # every caller-supplied buffer is checked before the library is called:
     # a short or wrongly typed gradient buffer would be written out of bounds

@@ -475,6 +475,37 @@ def test_kept_backward_sg(po, deg):
     assert po.device_errors() == 0
 
 
+@pytest.mark.parametrize("between", [False, True])
+def test_autograd_split(po, fog, between):
+    # the autograd function over 70000 rays (split render): its backward
+    # differentiates over the kept pieces, or, after another split render on
+    # the stream, walks the rays again; either is held to the oracle gradient
+    import torch
+
+    s, tree, ot = fog
+    tree.sigma.requires_grad_(True)
+    tree.sh.requires_grad_(True)
+    try:
+        o, d = scenes.random_rays(70000, 67, radius=2.5, spread=0.9)
+        og, dg = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (o, d))
+        g = np.random.default_rng(71).standard_normal((len(o), 3)).astype(np.float32)
+        rgb = po.render_rays_differentiable(tree, og, dg, stop_T=1e-4)
+        if between:
+            po.render_rays(tree, og, dg)  # other split work on the stream's queue
+        rgb.backward(torch.from_numpy(g).cuda())
+        torch.cuda.synchronize()
+        (ls, hs_), (lh, hh), n_str = gradcheck.grad_envelope(ot, o, d, g, (1.0, 1.0, 1.0), 1e-4)
+        a, b = gradcheck.to_cells(tree, tree.sigma.grad.cpu().numpy(), tree.sh.grad.cpu().numpy())
+        gradcheck.check(a, ls, hs_, f"autograd (between {between}) dsigma")
+        gradcheck.check(b, lh, hh, f"autograd (between {between}) dsh")
+    finally:
+        tree.sigma.requires_grad_(False)
+        tree.sh.requires_grad_(False)
+        tree.sigma.grad = None
+        tree.sh.grad = None
+    assert po.device_errors() == 0
+
+
 def test_kept_backward_refusals(po, fog):
     # the backward over kept pieces runs only right after the kept render of
     # the same rays and options on the same stream, and only once
