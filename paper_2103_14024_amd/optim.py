@@ -80,7 +80,6 @@ class Trainer:
         self.steps += 1
         return loss
 
-
     def save(self, path) -> None:
         """Checkpoints the fit: the tree's values, the step count and the
         batch generator's state (written with Tree.save)."""
