@@ -60,6 +60,21 @@ def test_loss_grad_and_sgd_kernels(po):
     want = p - 0.25 * gp
     L.call("po_sgd_step", 5003, p.data_ptr(), gp.data_ptr(), ctypes.c_float(0.25), 1, s)
     assert torch.allclose(p, want, rtol=1e-6, atol=1e-7) and gp.abs().max().item() == 0.0
+    # zero gradients and signed zeros: p - lr g bit for bit (lr a power of
+    # two, so the product is exact and the float32 subtraction rounds once,
+    # as the fused multiply-add does)
+    m = 4099
+    p = torch.rand(m, device="cuda", generator=g) - 0.5
+    gp = torch.rand(m, device="cuda", generator=g) - 0.5
+    p[::3] = 0.0
+    p[1::3] = -0.0
+    gp[::2] = 0.0
+    gp[1::4] = -0.0
+    want = (p.cpu() - 0.25 * gp.cpu()).view(torch.int32)
+    L.call("po_sgd_step", m, p.data_ptr(), gp.data_ptr(), ctypes.c_float(0.25), 1, s)
+    torch.cuda.synchronize()
+    assert torch.equal(p.cpu().view(torch.int32), want)
+    assert int((gp.view(torch.int32) != 0).sum()) == 0  # every gradient cleared to +0
 
 
 def test_loss_grad_large_and_gather(po):
