@@ -260,7 +260,7 @@ po_status po_render_rays(const po_tree* t, int64_t n, const float* d_origins, co
  * transmittance.  The colour equals the one-pass render (po_render_batch)
  * up to float rounding; where T lands within rounding of stop_T the two can
  * stop one cell apart, which moves at most stop_T of weight.  For this the
- * library keeps a work queue of about 400 MB per (device, stream), made on
+ * library keeps a work queue of about 200 MB per (device, stream), made on
  * the first such call and held until the process ends (if it cannot be
  * allocated, the image is rendered in one pass).  Calls on one stream are
  * ordered; calls on different streams use different queues.  Errors as for
@@ -276,7 +276,7 @@ po_status po_render_camera(const po_tree* t, const po_camera* cam, const po_rend
  * fixed array of 100,663,808 bytes that the library holds in a static
  * device variable, one copy on each GPU it runs on, kept until the
  * process ends.  Its device address is looked up on the first call on a
- * device.  The queue holds 64 regions of 8192 pieces (a quarter of the
+ * device.  The queue holds 64 regions of 8192 pieces (half of the
  * per-stream queue); a long walk that finds its region full is finished by
  * its own lane, which changes the speed, not the result beyond float
  * rounding.  Images of more than 2^22 pixels (4,194,304; e.g. 2048 x 2048)
@@ -484,7 +484,7 @@ po_status po_traversal_stats_rays(const po_tree* t, int64_t n, const float* d_or
 
 /* --------------------------------------------------------------- resources
  * po_reserve_queues: allocates now the work queue that split renders,
- * split ray lists and split backward passes on `stream` use (about 400 MB on
+ * split ray lists and split backward passes on `stream` use (about 200 MB on
  * the current device, held until po_release_queues or the end of the
  * process), so that the first such call on the stream allocates nothing.
  * Does nothing if the queue exists.  Errors: PO_ERR_DEVICE (allocation

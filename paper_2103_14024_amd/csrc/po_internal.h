@@ -92,7 +92,7 @@ struct KJob {
 // nothing.  A walk whose region is full finishes in its own lane, so the size
 // changes the speed, never the result.
 #ifndef PO_SPLIT_REGION_SLOTS
-#define PO_SPLIT_REGION_SLOTS 32768
+#define PO_SPLIT_REGION_SLOTS 16384
 #endif
 constexpr int kSplitRegions = 64;
 constexpr int kSplitRegionSlots = PO_SPLIT_REGION_SLOTS;
