@@ -213,6 +213,69 @@ def test_split_repeated_and_small(po, fog):
     assert po.device_errors() == 0
 
 
+def test_split_passes_share_the_queue(po, fog):
+    # every kind of split pass, one after another on one stream's queue,
+    # against the same pass run alone on a fresh queue (colours bit for bit;
+    # gradients within the reordering of their float atomics)
+    import torch
+
+    s, tree, ot = fog
+    cam, _ = _cam(po, 256, 256, seed=5)
+    cam2, _ = _cam(po, 320, 256, seed=6)
+    o, d = scenes.random_rays(70000, 91, radius=2.5, spread=0.9)
+    og, dg = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (o, d))
+    gg = torch.from_numpy(np.random.default_rng(93).standard_normal((len(o), 3)).astype(np.float32)).cuda()
+
+    def camera():
+        return po.render_camera(tree, cam, stop_T=1e-4)
+
+    def rays():
+        return po.render_rays(tree, og, dg, stop_T=1e-4)
+
+    def batch():
+        a = torch.empty((256, 256, 3), device="cuda")
+        b = torch.empty((256, 320, 3), device="cuda")
+        po.render_batch([po.Job(tree, cam, a), po.Job(tree, cam2, b)])
+        return torch.cat([a.reshape(-1), b.reshape(-1)])
+
+    def keep_and_backward():
+        slot = torch.empty(len(o), dtype=torch.int32, device="cuda")
+        rk = po.render_rays_keep(tree, og, dg, slot, stop_T=1e-4)
+        ks = torch.zeros((tree.n_leaves,), device="cuda")
+        ksh = torch.zeros((tree.n_leaves, tree.stride), device="cuda")
+        po.render_rays_backward_kept(tree, og, dg, rk, gg, slot, ks, ksh, stop_T=1e-4)
+        return rk, ks, ksh
+
+    def backward():
+        gs, gsh = po.render_rays_backward(tree, og, dg, rays(), gg, stop_T=1e-4)
+        return gs, gsh
+
+    passes = [("camera", camera), ("rays", rays), ("batch", batch), ("keep", keep_and_backward),
+              ("backward", backward), ("camera again", camera), ("keep again", keep_and_backward)]
+    alone = {}
+    for name, f in passes:
+        po.release_queues()
+        alone[name] = f()
+        torch.cuda.synchronize()
+    po.release_queues()
+    _say("split passes in a row on one queue")
+    for rnd in range(2):
+        for name, f in passes:
+            got = f()
+            torch.cuda.synchronize()
+            want = alone[name]
+            if not isinstance(got, tuple):
+                assert torch.equal(got, want), f"{name} (round {rnd})"
+                continue
+            for i, (x, y) in enumerate(zip(got, want)):
+                if x.shape[-1] == 3 and x.dim() == 2 and x.shape[0] == len(o):
+                    assert torch.equal(x, y), f"{name} colours (round {rnd})"
+                else:
+                    scale = float(y.abs().max())
+                    assert float((x - y).abs().max()) <= 1e-5 * scale, f"{name} output {i} (round {rnd})"
+    assert po.device_errors() == 0
+
+
 @pytest.mark.parametrize("deg,sg,dtype", [(0, False, "f32"), (1, False, "f16"), (2, False, "f32"), (4, False, "f32"),
                                           (4, True, "f16")])
 def test_split_every_basis(po, deg, sg, dtype):
