@@ -378,6 +378,21 @@ po_status po_sgd_step(int64_t n, float* d_param, float* d_grad, float lr, int32_
  * n_src < 1), PO_ERR_DEVICE. */
 po_status po_gather_rays(int64_t n, const int64_t* d_idx, int64_t n_src, const float* d_o, const float* d_d,
                          const float* d_t, float* d_bo, float* d_bd, float* d_bt, void* stream);
+/* po_draw_batch: a training batch drawn on the device (Sec. 4.3: random rays
+ * of the training images, uniform with replacement), so that a step needs no
+ * index array: row i < n is row j_i = floor(z_i * n_src / 2^64) of the
+ * source arrays, gathered as po_gather_rays gathers, where z_i is element
+ * first + i (counting from 0) of the SplitMix64 sequence of `seed` (Steele,
+ * Lea and Flood, OOPSLA 2014: z = seed + (k + 1) * 0x9E3779B97F4A7C15, then
+ * z ^= z >> 30, z *= 0xBF58476D1CE4E5B9, z ^= z >> 27, z *=
+ * 0x94D049BB133111EB, z ^= z >> 31).  Consecutive batches of one fit take
+ * consecutive ranges of the sequence (first = step * n), so a fit resumes
+ * from (seed, step).  If d_sq_sum is not NULL, d_sq_sum[0] is set to 0 (the
+ * accumulator po_mse_grad adds the batch's squared errors to).  Errors:
+ * PO_ERR_INVALID (n < 0 or n >= 2^31, n_src < 1, NULL arrays with n > 0),
+ * PO_ERR_DEVICE. */
+po_status po_draw_batch(int64_t n, uint64_t seed, uint64_t first, int64_t n_src, const float* d_o, const float* d_d,
+                        const float* d_t, float* d_bo, float* d_bd, float* d_bt, float* d_sq_sum, void* stream);
 
 /* ---------------------------------------------------------------- batches
  * One job renders the 16x16 tiles [tile_begin, tile_end) of one camera

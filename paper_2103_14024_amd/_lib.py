@@ -81,6 +81,7 @@ _SIGS = {
     "po_mse_grad": [_I64, _P, _P, ctypes.c_float, _P, _P, _P],
     "po_sgd_step": [_I64, _P, _P, ctypes.c_float, _I32, _P],
     "po_gather_rays": [_I64, _P, _I64, _P, _P, _P, _P, _P, _P, _P],
+    "po_draw_batch": [_I64, ctypes.c_uint64, ctypes.c_uint64, _I64, _P, _P, _P, _P, _P, _P, _P, _P],
     "po_leaf_weights": [_P, ctypes.POINTER(po_camera), ctypes.POINTER(po_render_opts), _I32, _P, _P, _P],
     "po_tree_leaf_cells": [ctypes.POINTER(po_tree_desc), _I64, _P, _I64, _P],
     "po_device_errors": [ctypes.POINTER(_I64)],

@@ -944,6 +944,18 @@ po_status po_gather_rays(int64_t n, const int64_t* d_idx, int64_t n_src, const f
     return ok();
 }
 
+po_status po_draw_batch(int64_t n, uint64_t seed, uint64_t first, int64_t n_src, const float* d_o, const float* d_d,
+                        const float* d_t, float* d_bo, float* d_bd, float* d_bt, float* d_sq_sum, void* stream) {
+    if (n < 0 || n >= (1ll << 31)) return fail(PO_ERR_INVALID, "n = %lld out of range", (long long)n);
+    if (n_src < 1 || n_src >= (1ll << 40)) return fail(PO_ERR_INVALID, "n_src = %lld out of range", (long long)n_src);
+    if (n == 0) return ok();
+    if (!d_o || !d_d || !d_t || !d_bo || !d_bd || !d_bt) return fail(PO_ERR_INVALID, "NULL array");
+    hipError_t e = po_launch_draw_batch(n, seed, first, n_src, d_o, d_d, d_t, d_bo, d_bd, d_bt, d_sq_sum,
+                                        (hipStream_t)stream);
+    if (e != hipSuccess) return device_fail(e, "draw_batch launch");
+    return ok();
+}
+
 po_status po_camera_tiles(const po_camera* cam, int32_t* n_tiles) {
     if (po_status s = check_camera(cam)) return s;
     if (!n_tiles) return fail(PO_ERR_INVALID, "n_tiles is NULL");

@@ -262,6 +262,9 @@ hipError_t po_launch_mse_grad(int64_t n, const float* rgb, const float* target, 
 hipError_t po_launch_sgd(int64_t n, float* param, float* grad, float lr, bool zero_grad, hipStream_t s);
 hipError_t po_launch_gather_rays(int64_t n, const int64_t* idx, int64_t n_src, const float* o, const float* d,
                                  const float* t, float* bo, float* bd, float* bt, hipStream_t s);
+hipError_t po_launch_draw_batch(int64_t n, uint64_t seed, uint64_t first, int64_t n_src, const float* o,
+                               const float* d, const float* t, float* bo, float* bd, float* bt, float* sq_sum,
+                               hipStream_t s);
 hipError_t po_read_device_errors(unsigned long long* out);
 // Kernel variant a tree renders with (dtype, K, record-load plan); jobs of one
 // batched launch must share it.

@@ -2100,6 +2100,34 @@ __global__ __launch_bounds__(256) void k_gather_rays(int64_t n, const int64_t* _
     }
 }
 
+// A training batch drawn on the device: element `first + i` of the SplitMix64
+// sequence of `seed` (Steele, Lea and Flood, "Fast splittable pseudorandom
+// number generators", OOPSLA 2014: the state advances by the golden-ratio
+// increment and each output is the state passed through the variant-13
+// finaliser) picks row floor(z * n_src / 2^64), and the three rows are
+// gathered.  Thread 0 also clears the loss accumulator of the batch.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__global__ __launch_bounds__(256) void k_draw_batch(int64_t n, uint64_t seed, uint64_t first, int64_t n_src,
+                                                    const float* __restrict__ o, const float* __restrict__ d,
+                                                    const float* __restrict__ t, float* __restrict__ bo,
+                                                    float* __restrict__ bd, float* __restrict__ bt,
+                                                    float* __restrict__ sq_sum) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    if (i == 0 && sq_sum) sq_sum[0] = 0.0f;
+    const int64_t j = (int64_t)__umul64hi(splitmix64(seed, first + (uint64_t)i), (uint64_t)n_src);
+    for (int c = 0; c < 3; ++c) {
+        bo[3 * i + c] = o[3 * j + c];
+        bd[3 * i + c] = d[3 * j + c];
+        bt[3 * i + c] = t[3 * j + c];
+    }
+}
+
 // Plain SGD on the leaf values (Sec. 4.3): p -= lr g, optionally clearing g.
 __global__ __launch_bounds__(256) void k_sgd(int64_t n, float* __restrict__ p, float* __restrict__ g, float lr,
                                              int zero_grad) {
@@ -2617,6 +2645,14 @@ hipError_t po_launch_gather_rays(int64_t n, const int64_t* idx, int64_t n_src, c
                                  const float* t, float* bo, float* bd, float* bt, hipStream_t s) {
     hipLaunchKernelGGL(k_gather_rays, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, idx, n_src, o, d, t,
                        bo, bd, bt);
+    return hipGetLastError();
+}
+
+hipError_t po_launch_draw_batch(int64_t n, uint64_t seed, uint64_t first, int64_t n_src, const float* o,
+                               const float* d, const float* t, float* bo, float* bd, float* bt, float* sq_sum,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_draw_batch, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, seed, first, n_src, o, d,
+                       t, bo, bd, bt, sq_sum);
     return hipGetLastError();
 }
 

@@ -6,8 +6,8 @@ eqn:nerfloss; here the mean over the batch and the colour channels) and plain
 SGD.  One step: forward render of a random ray batch that keeps its pieces
 (the first pass of the App. B.3 scheme), loss gradient, backward replay with
 atomics over the same pieces (second pass), SGD updates that also clear the
-gradients -- library calls only.  torch holds the buffers and draws the
-batch indices.
+gradients -- library calls only, the batch drawn on the device from a
+counter-based generator (po_draw_batch).  torch holds the buffers.
 """
 from __future__ import annotations
 
@@ -21,7 +21,9 @@ class Trainer:
     """SGD on tree.sigma and tree.sh (float32 tree) against a ray dataset.
 
     origins, dirs, target: (N, 3) float32 device tensors (all training
-    pixels); each step draws `batch` of them uniformly with replacement."""
+    pixels); each step draws `batch` of them uniformly with replacement, step
+    k taking elements [k batch, (k + 1) batch) of the SplitMix64 sequence of
+    `seed`."""
 
     def __init__(self, tree, origins, dirs, target, lr_sigma, lr_sh, batch=65536, bg=(1.0, 1.0, 1.0), stop_T=1e-4,
                  seed=0):
@@ -33,8 +35,9 @@ class Trainer:
         self.lr_sigma, self.lr_sh, self.batch = float(lr_sigma), float(lr_sh), int(batch)
         self.bg, self.stop_T = tuple(bg), float(stop_T)
         dev = origins.device
-        self.gen = torch.Generator(device=dev)
-        self.gen.manual_seed(seed)
+        if not 0 <= int(seed) < 2 ** 64:
+            raise ValueError("seed must fit in 64 bits")
+        self.seed = int(seed)
         f = dict(dtype=torch.float32, device=dev)
         self.bo = torch.empty((batch, 3), **f)
         self.bd = torch.empty((batch, 3), **f)
@@ -60,10 +63,10 @@ class Trainer:
         n = self.batch
         tr = self.tree
         with torch.cuda.stream(ts):
-            idx = torch.randint(0, self.o.shape[0], (n,), device=self.o.device, generator=self.gen)
-            L.call("po_gather_rays", n, idx.data_ptr(), self.o.shape[0], self.o.data_ptr(), self.d.data_ptr(),
-                   self.t.data_ptr(), self.bo.data_ptr(), self.bd.data_ptr(), self.bt.data_ptr(), s)
-            self.sq.zero_()
+            # the batch, and the loss accumulator cleared
+            L.call("po_draw_batch", n, ctypes.c_uint64(self.seed), ctypes.c_uint64(self.steps * n), self.o.shape[0],
+                   self.o.data_ptr(), self.d.data_ptr(), self.t.data_ptr(), self.bo.data_ptr(), self.bd.data_ptr(),
+                   self.bt.data_ptr(), self.sq.data_ptr(), s)
             # the render keeps its pieces for the backward (App. B.3's two passes)
             L.call("po_render_rays_keep", tr.handle, n, self.bo.data_ptr(), self.bd.data_ptr(),
                    ctypes.byref(self.opts), self.rgb.data_ptr(), self.slot.data_ptr(), s)
@@ -82,13 +85,15 @@ class Trainer:
 
     def save(self, path) -> None:
         """Checkpoints the fit: the tree's values, the step count and the
-        batch generator's state (written with Tree.save)."""
-        self.tree.save(path, step=self.steps, rng_state=self.gen.get_state().numpy())
+        batch seed (written with Tree.save)."""
+        import numpy as np
+
+        self.tree.save(path, step=self.steps, seed=np.uint64(self.seed))
 
     def load(self, path) -> None:
         """Resumes from a file written by save: the leaf values are copied into
         this trainer's tree in place (its structure must match the file's), and
-        the step count and the generator state are restored."""
+        the step count and the batch seed are restored."""
         import numpy as np
         import torch
 
@@ -100,12 +105,12 @@ class Trainer:
                 or tuple(f["sh"].shape) != tuple(tr.sh.shape)
                 or not np.array_equal(f["child"], tr.child.cpu().numpy())):
             raise ValueError("checkpoint tree does not match the trainer's tree")
-        if "step" not in meta or "rng_state" not in meta:
+        if "step" not in meta or "seed" not in meta:
             raise ValueError("checkpoint lacks the trainer state")
         tr.sigma.copy_(torch.from_numpy(f["sigma"]))
         tr.sh.copy_(torch.from_numpy(f["sh"]))
         self.steps = int(meta["step"])
-        self.gen.set_state(torch.from_numpy(np.ascontiguousarray(meta["rng_state"], np.uint8)))
+        self.seed = int(np.asarray(meta["seed"]).astype(np.uint64))
 
 
 def training_set(gt_tree, cams, bg=(1.0, 1.0, 1.0), stop_T=1e-4, device="cuda"):

@@ -213,6 +213,39 @@ def test_split_repeated_and_small(po, fog):
     assert po.device_errors() == 0
 
 
+def test_reserve_queues(po, fog):
+    # po_reserve_queues allocates a stream's queue up front (~201 MB); a
+    # split render on that stream then allocates nothing, and a second
+    # reservation of the same stream does nothing
+    import torch
+
+    s, tree, ot = fog
+    po.release_queues()
+    st = torch.cuda.Stream()
+    cam, _ = _cam(po, 256, 256, seed=3)
+    out = torch.empty((256, 256, 3), device="cuda")
+    ref = po.render_camera(tree, cam, stop_T=1e-4)  # the default stream's own queue
+    torch.cuda.synchronize()
+    f0, _ = torch.cuda.mem_get_info()
+    po.reserve_queues(stream=st)
+    torch.cuda.synchronize()
+    f1, _ = torch.cuda.mem_get_info()
+    _say(f"reserve: {(f0 - f1) / 1e6:.1f} MB")
+    assert f0 - f1 >= 190e6
+    with torch.cuda.stream(st):
+        po.render_camera(tree, cam, stop_T=1e-4, out=out, stream=st)
+        po.reserve_queues(stream=st)
+    st.synchronize()
+    f2, _ = torch.cuda.mem_get_info()
+    assert abs(f2 - f1) < 16e6
+    assert torch.equal(out, ref)
+    po.release_queues()
+    torch.cuda.synchronize()
+    f3, _ = torch.cuda.mem_get_info()
+    assert f3 - f2 >= 380e6  # both queues freed
+    assert po.device_errors() == 0
+
+
 def test_split_passes_share_the_queue(po, fog):
     # every kind of split pass, one after another on one stream's queue,
     # against the same pass run alone on a fresh queue (colours bit for bit;

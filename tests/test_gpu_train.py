@@ -77,6 +77,41 @@ def test_loss_grad_and_sgd_kernels(po):
     assert int((gp.view(torch.int32) != 0).sum()) == 0  # every gradient cleared to +0
 
 
+def test_draw_batch(po):
+    # the device draw against the SplitMix64 reference: the same rows, and
+    # the loss accumulator cleared
+    import ctypes
+
+    import torch
+
+    from paper_2103_14024_amd import _lib as L
+    from splitmix import draw_rows
+
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    n_src, n = 123_457, 10_007
+    o, d, t = (torch.rand((n_src, 3), device="cuda", generator=g) for _ in range(3))
+    bo, bd, bt = (torch.empty((n, 3), device="cuda") for _ in range(3))
+    sq = torch.full((1,), 5.0, device="cuda")
+    seed, first = 0xDEADBEEF12345678, 3 * n
+    L.call("po_draw_batch", n, ctypes.c_uint64(seed), ctypes.c_uint64(first), n_src, o.data_ptr(), d.data_ptr(),
+           t.data_ptr(), bo.data_ptr(), bd.data_ptr(), bt.data_ptr(), sq.data_ptr(), s)
+    torch.cuda.synchronize()
+    idx = torch.tensor(draw_rows(seed, first, n, n_src), device="cuda")
+    assert torch.equal(bo, o[idx]) and torch.equal(bd, d[idx]) and torch.equal(bt, t[idx])
+    assert sq.item() == 0.0
+    # no accumulator: nothing else written; n = 0 does nothing
+    L.call("po_draw_batch", 5, ctypes.c_uint64(1), ctypes.c_uint64(0), n_src, o.data_ptr(), d.data_ptr(),
+           t.data_ptr(), bo.data_ptr(), bd.data_ptr(), bt.data_ptr(), None, s)
+    L.call("po_draw_batch", 0, ctypes.c_uint64(1), ctypes.c_uint64(0), n_src, None, None, None, None, None, None,
+           None, s)
+    torch.cuda.synchronize()
+    assert torch.equal(bo[:5], o[torch.tensor(draw_rows(1, 0, 5, n_src), device="cuda")])
+    with pytest.raises(L.PlenOctreeError):
+        L.call("po_draw_batch", 5, ctypes.c_uint64(1), ctypes.c_uint64(0), 0, o.data_ptr(), d.data_ptr(),
+               t.data_ptr(), bo.data_ptr(), bd.data_ptr(), bt.data_ptr(), None, s)
+
+
 def test_loss_grad_large_and_gather(po):
     # the loss gradient over more rays than one grid pass covers (grid-stride
     # loop, one atomic per workgroup) and the batch gather against its
