@@ -105,7 +105,7 @@ constexpr int kSplitMaxChunks = 16;
 #define PO_CHUNK_STEPS 24
 #endif
 #ifndef PO_SUB_STEPS
-#define PO_SUB_STEPS 12
+#define PO_SUB_STEPS 10
 #endif
 #ifndef PO_CHUNK_CAP
 #define PO_CHUNK_CAP 24
@@ -120,11 +120,13 @@ constexpr int kSplitMaxChunks = 16;
 // its first walk, so its rays walk further before the hand-off and fewer of
 // them wait in the chunk queues (depth-9 scene, float32 leaves: 800x800 0.588
 // -> 0.551 ms, 1920x1080 1.78 -> 1.38 ms against a fixed 28 cells; the
-// regions of a 1920x1080 frame no longer overflow).  Ray-list passes keep
-// PO_SPLIT_STEPS: their render and backward must cut the rays alike.
+// regions of a 1920x1080 frame no longer overflow; 18 cells per round with
+// 10-cell sub-chunks instead of 16 with 12: 800x800 0.5365 against 0.5409 ms,
+// 1920x1080 1.357 against 1.352 ms).  Ray-list passes keep PO_SPLIT_STEPS:
+// their render and backward must cut the rays alike.
 constexpr int64_t kResidentWaves = 4096;
 inline int po_camera_split_steps(int64_t waves) {
-    const int64_t s = 20 + 16 * waves / kResidentWaves;
+    const int64_t s = 20 + 18 * waves / kResidentWaves;
     return (int)(s < PO_SPLIT_STEPS ? PO_SPLIT_STEPS : s > 192 ? 192 : s);
 }
 // piece sizes of ray-list passes (render and backward) of fewer than
